@@ -1,0 +1,232 @@
+"""FP64 CPU oracle for disconnected fermion loops (arXiv:1108.2473).
+
+TEST INFRASTRUCTURE ONLY.  This package is the checker for the GPU library:
+only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark may import it.  It shares no code with the GPU path; both follow
+the paper's definitions independently.
+
+Canonical layouts (numpy complex128, C order):
+  gauge field   U[4][V][3][3]      (direction mu = x,y,z,t; row, column)
+  spinors       psi[nrhs][V][4][3] (spin, colour); a single spinor may be
+                passed as [V][4][3]
+with the lexicographic site index s = x + Lx*(y + Ly*(z + Lz*t)).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_long_p = ctypes.POINTER(ctypes.c_long)
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+def _load():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    lib = ctypes.CDLL(_build.LIB)
+    i, d, l, u64 = ctypes.c_int, ctypes.c_double, ctypes.c_long, ctypes.c_uint64
+    ip, dp, lp = _c_int_p, _c_double_p, _c_long_p
+    lib.or_num_threads.restype = i
+    lib.or_gamma.argtypes = [i, i, dp]
+    lib.or_hop.argtypes = [ip, i, i, dp, dp, dp, i, i]
+    lib.or_apply_D.argtypes = [ip, i, i, d, dp, dp, dp, i, i]
+    lib.or_apply_Dhat.argtypes = [ip, i, i, d, dp, dp, dp, i]
+    lib.or_solve.argtypes = [ip, i, i, d, dp, dp, dp, i, d, i, i, ip, dp]
+    lib.or_solve.restype = i
+    lib.or_loops_exact.argtypes = [ip, i, i, d, dp, ip, i, ip, i, d, i, dp, dp]
+    lib.or_loops_exact.restype = i
+    lib.or_loops_exact_sites.argtypes = [ip, i, i, d, dp, lp, l, ip, i, d, i, dp, dp]
+    lib.or_loops_exact_sites.restype = i
+    lib.or_splitmix64.argtypes = [u64, u64]
+    lib.or_splitmix64.restype = u64
+    lib.or_noise.argtypes = [i, u64, l, ip, dp]
+    lib.or_loops_tsm.argtypes = [ip, i, i, d, dp, i, u64, l, i, i, d, d, i, i, i, ip, i, i, dp]
+    lib.or_loops_tsm.restype = i
+    lib.or_loops_stochastic.argtypes = [ip, i, i, d, dp, i, u64, l, i, i, i, i, ip, i, d, i, dp]
+    lib.or_loops_stochastic.restype = i
+    lib.or_loops_grad.argtypes = [ip, i, i, d, dp, ip, i, ip, i, dp, d, i, dp, dp]
+    lib.or_loops_grad.restype = i
+    _LIB = lib
+    return lib
+
+
+def _dims(dims):
+    return (ctypes.c_int * 4)(*[int(v) for v in dims])
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_c_double_p)
+
+
+def _cplx(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _ints(seq):
+    seq = [int(v) for v in seq]
+    return (ctypes.c_int * max(1, len(seq)))(*seq), len(seq)
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
+
+
+def gamma(mask: int, basis: int = 0) -> np.ndarray:
+    """Gamma = g1^b0 g2^b1 g3^b2 g4^b3 for a 4-bit mask (g5 = mask 15)."""
+    out = np.zeros((4, 4), dtype=np.complex128)
+    _load().or_gamma(basis, mask, _ptr(out))
+    return out
+
+
+def hop(U, psi, dims, bc_t, out_parity=-1, dagger=False, basis=0):
+    """Hopping term sum_mu [(1-g_mu)U_mu(x)psi(x+mu) + (1+g_mu)U_mu(x-mu)^+psi(x-mu)]."""
+    U = _cplx(U)
+    psi = _cplx(psi)
+    out = np.zeros_like(psi)
+    _load().or_hop(_dims(dims), bc_t, basis, _ptr(U), _ptr(psi), _ptr(out), out_parity,
+                   int(dagger))
+    return out
+
+
+def apply_D(U, psi, dims, bc_t, kappa, dagger=False, basis=0):
+    """Wilson-Dirac operator D = 1 - kappa*Hop (or D^+) applied to psi."""
+    U = _cplx(U)
+    psi = _cplx(psi)
+    V = int(np.prod(dims))
+    nrhs = psi.size // (V * 12)
+    out = np.zeros_like(psi)
+    _load().or_apply_D(_dims(dims), bc_t, basis, kappa, _ptr(U), _ptr(psi), _ptr(out), nrhs,
+                       int(dagger))
+    return out
+
+
+def apply_Dhat(U, psi_even, dims, bc_t, kappa, dagger=False, basis=0):
+    """Schur operator 1 - kappa^2 H_eo H_oe on a full-lattice vector (odd part ignored)."""
+    U = _cplx(U)
+    psi = _cplx(psi_even)
+    out = np.zeros_like(psi)
+    _load().or_apply_Dhat(_dims(dims), bc_t, basis, kappa, _ptr(U), _ptr(psi), _ptr(out),
+                          int(dagger))
+    return out
+
+
+def solve(U, b, dims, bc_t, kappa, tol=1e-13, max_iter=20000, method=0, basis=0):
+    """Solve D x = b to relative full-operator residual tol.
+
+    method 0: even-odd BiCGStab with CGNR fallback; 1: full BiCGStab;
+    2: even-odd CGNR.  Returns (x, iters, resid, n_failed).
+    """
+    U = _cplx(U)
+    b = _cplx(b)
+    V = int(np.prod(dims))
+    nrhs = b.size // (V * 12)
+    x = np.zeros_like(b)
+    iters = np.zeros(nrhs, dtype=np.int32)
+    resid = np.zeros(nrhs, dtype=np.float64)
+    fails = _load().or_solve(_dims(dims), bc_t, basis, kappa, _ptr(U), _ptr(b), _ptr(x), nrhs,
+                             tol, max_iter, method, iters.ctypes.data_as(_c_int_p),
+                             _ptr(resid))
+    return x, iters, resid, fails
+
+
+def loops_exact(U, dims, bc_t, kappa, t0, gammas, tol=1e-13, max_iter=20000, basis=0,
+                want_S=False):
+    """Exact loops L_Gamma(y) = Tr[Gamma G(y;y)] on whole timeslices.
+
+    Returns L [ngamma][nt][Vs] (and S [nt][Vs][4][4] when want_S).
+    """
+    U = _cplx(U)
+    t_arr, nt = _ints(t0)
+    g_arr, ng = _ints(gammas)
+    Vs = int(dims[0] * dims[1] * dims[2])
+    L = np.zeros((ng, nt, Vs), dtype=np.complex128)
+    S = np.zeros((nt, Vs, 4, 4), dtype=np.complex128) if want_S else None
+    fails = _load().or_loops_exact(_dims(dims), bc_t, basis, kappa, _ptr(U), t_arr, nt, g_arr,
+                                   ng, tol, max_iter, _ptr(L),
+                                   _ptr(S) if want_S else None)
+    if fails:
+        raise RuntimeError(f"oracle: {fails} exact-loop solves missed tol={tol}")
+    return (L, S) if want_S else L
+
+
+def loops_exact_sites(U, dims, bc_t, kappa, sites, gammas, tol=1e-13, max_iter=20000,
+                      basis=0, want_S=False):
+    """Exact loops at an explicit list of lexicographic sites: L [ngamma][nsites]."""
+    U = _cplx(U)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    g_arr, ng = _ints(gammas)
+    L = np.zeros((ng, sites.size), dtype=np.complex128)
+    S = np.zeros((sites.size, 4, 4), dtype=np.complex128) if want_S else None
+    fails = _load().or_loops_exact_sites(_dims(dims), bc_t, basis, kappa, _ptr(U),
+                                         sites.ctypes.data_as(_c_long_p), sites.size, g_arr,
+                                         ng, tol, max_iter, _ptr(L),
+                                         _ptr(S) if want_S else None)
+    if fails:
+        raise RuntimeError(f"oracle: {fails} exact-loop solves missed tol={tol}")
+    return (L, S) if want_S else L
+
+
+NOISE_Z4, NOISE_CZ2, NOISE_Z2 = 0, 1, 2
+DIL_TIME, DIL_SPIN, DIL_COLOUR, DIL_EVENODD, DIL_CUBIC = 1, 2, 4, 8, 16
+
+
+def splitmix64(seed: int, k: int) -> int:
+    """k-th output (0-based) of SplitMix64 started from state `seed`."""
+    return int(_load().or_splitmix64(seed & (2**64 - 1), k & (2**64 - 1)))
+
+
+def noise(noise_type, seed, r, dims):
+    """Noise vector xi_r [V][4][3] of the counter-based generator."""
+    V = int(np.prod(dims))
+    out = np.zeros((V, 4, 3), dtype=np.complex128)
+    _load().or_noise(noise_type, seed & (2**64 - 1), r, _dims(dims), _ptr(out))
+    return out
+
+
+def loops_tsm(U, dims, bc_t, kappa, noise_type, seed, r0, n_lp, n_hp, tol_lp, tol_hp,
+              dilution, t_begin, t_end, gammas, max_iter=20000, basis=0):
+    """Truncated-solver-method estimate L [ngamma][t_end-t_begin][Vs]."""
+    U = _cplx(U)
+    g_arr, ng = _ints(gammas)
+    Vs = int(dims[0] * dims[1] * dims[2])
+    L = np.zeros((ng, t_end - t_begin, Vs), dtype=np.complex128)
+    fails = _load().or_loops_tsm(_dims(dims), bc_t, basis, kappa, _ptr(U), noise_type,
+                                 seed & (2**64 - 1), r0, n_lp, n_hp, tol_lp, tol_hp, dilution,
+                                 t_begin, t_end, g_arr, ng, max_iter, _ptr(L))
+    if fails:
+        raise RuntimeError(f"oracle: {fails} high-precision solves missed tol={tol_hp}")
+    return L
+
+
+def loops_stochastic(U, dims, bc_t, kappa, noise_type, seed, r0, n_noise, dilution, t_begin,
+                     t_end, gammas, tol=1e-13, max_iter=20000, basis=0):
+    """Plain diluted stochastic estimate, Eq. (loop stochastic): [ngamma][nt][Vs]."""
+    return loops_tsm(U, dims, bc_t, kappa, noise_type, seed, r0, n_noise, 0, tol, tol,
+                     dilution, t_begin, t_end, gammas, max_iter=max_iter, basis=basis)
+
+
+def loops_grad(U, dims, bc_t, kappa, t0, gammas, w, tol=1e-13, max_iter=20000, basis=0):
+    """Adjoint gradient of F = Re sum conj(w) L for exact timeslice loops.
+
+    w: complex [ngamma][nt][Vs].  Returns (dU [4][V][3][3], dkappa) with
+    dU = dF/dRe U + i dF/dIm U.
+    """
+    U = _cplx(U)
+    t_arr, nt = _ints(t0)
+    g_arr, ng = _ints(gammas)
+    w = _cplx(w)
+    V = int(np.prod(dims))
+    dU = np.zeros((4, V, 3, 3), dtype=np.complex128)
+    dk = ctypes.c_double(0.0)
+    fails = _load().or_loops_grad(_dims(dims), bc_t, basis, kappa, _ptr(U), t_arr, nt, g_arr,
+                                  ng, _ptr(w), tol, max_iter, _ptr(dU), ctypes.byref(dk))
+    if fails:
+        raise RuntimeError(f"oracle: {fails} gradient solves missed tol={tol}")
+    return dU, dk.value
