@@ -1,0 +1,248 @@
+/*
+ * floop.h -- C ABI of the MI355X (gfx950) library for disconnected fermion
+ * loops L(x) = Tr[Gamma G(x;x)] (Alexandrou, Hadjiyiannakou, Koutsou,
+ * O Cais, Strelchenko, arXiv:1108.2473, Eq. (loop)).
+ *
+ * The library evaluates the loops exactly (12 V_s point-source inversions
+ * per timeslice, Sec. II) or stochastically (diluted noise, Eq. (loop
+ * stochastic), and the truncated solver method, Sec. II and III), each
+ * inversion an even-odd preconditioned BiCGStab or CGNR solve of the
+ * Wilson-Dirac operator run by hand-written HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  lattice   extents dims = {Lx, Ly, Lz, Lt}, each even and >= 2; site
+ *            index s = x + Lx*(y + Ly*(z + Lz*t)); V = Lx*Ly*Lz*Lt,
+ *            Vs = Lx*Ly*Lz.  Direction mu = 0..3 is x, y, z, t.
+ *  operator  (D psi)(x) = psi(x) - kappa sum_mu [ (1-g_mu) U_mu(x) psi(x+mu)
+ *                                             + (1+g_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ *            (N_f=2 Wilson fermions at hopping parameter kappa, Sec. II;
+ *            the paper does not write the form, this is the r=1 Wilson
+ *            operator in hopping normalisation).  Space is periodic; a hop
+ *            across the time boundary is multiplied by bc_t.  Links carry
+ *            no boundary phase.
+ *  gammas    Hermitian chiral basis: g_k = [[0,-i s_k],[i s_k,0]],
+ *            g_4 = [[0,1],[1,0]], g_5 = g1 g2 g3 g4 = diag(1,1,-1,-1).
+ *            A Gamma insertion is a 4-bit mask: Gamma = g1^b0 g2^b1 g3^b2 g4^b3
+ *            (1 -> 0, g_mu -> 1 << (mu-1), g_5 -> 15).  The paper's set
+ *            Gamma = 1, g_5, g_mu is {0, 15, 1, 2, 4, 8}.
+ *  gauge     double U[4][V][3][3][2]: U_mu(s), row, column, (re, im).
+ *            Must be SU(3) to 1e-10 when 12-real link storage is used.
+ *  spinors   double psi[nrhs][V][4][3][2]: spin, colour, (re, im).
+ *  loops     double L[ngamma][nt][Vs][2] (complex, per Gamma, timeslice,
+ *            spatial site xs = x + Lx*(y + Ly*z)).
+ *  where     FL_HOST: pointers are host memory; FL_DEVICE: device memory
+ *            on the context's device, used in place on the context stream.
+ *  ownership the caller allocates every input and output; the library
+ *            copies what it needs and keeps no caller pointer past return.
+ *  errors    every call returns an fl_status; the text of the last error
+ *            of a context is fl_last_error(ctx).  Arguments are checked
+ *            before any device work is launched.  FL_ERR_NOCONV is not
+ *            fatal: outputs hold the best iterate and the stats are filled.
+ *  threads   a context is not thread-safe; use one per host thread.
+ */
+#ifndef FLOOP_H
+#define FLOOP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fl_ctx fl_ctx;
+
+typedef enum {
+    FL_OK = 0,
+    FL_ERR_ARG = -1,       /* invalid argument (checked before any launch) */
+    FL_ERR_STATE = -2,     /* missing set-up (gauge field, kappa) */
+    FL_ERR_DEVICE = -3,    /* HIP runtime error */
+    FL_ERR_NOMEM = -4,     /* device allocation failed */
+    FL_ERR_NOCONV = -5,    /* a solve missed its tolerance within max_iter */
+    FL_ERR_BREAKDOWN = -6  /* Krylov breakdown with no fallback left */
+} fl_status;
+
+typedef enum { FL_HOST = 0, FL_DEVICE = 1 } fl_where;
+
+typedef enum { FL_PREC_F64 = 0, FL_PREC_F32 = 1, FL_PREC_BF16 = 2 } fl_prec;
+
+typedef enum { FL_SOLVER_BICGSTAB = 0, FL_SOLVER_CGNR = 1 } fl_solver_kind;
+
+typedef enum { FL_NOISE_Z4 = 0, FL_NOISE_CZ2 = 1, FL_NOISE_Z2 = 2 } fl_noise_kind;
+
+/* dilution bits (Sec. II): time, spin (x4), colour (x3), even-odd space
+ * (x2), cubic (x8, one class per vertex of the elementary 3-cube) */
+enum { FL_DIL_TIME = 1, FL_DIL_SPIN = 2, FL_DIL_COLOUR = 4, FL_DIL_EVENODD = 8,
+       FL_DIL_CUBIC = 16 };
+
+/*
+ * Solver parameters.  The stopping rule is the paper's (Sec. III): the
+ * relative deviation |D x - b| / |b| of the full Wilson-Dirac operator.
+ *  solver      BiCGStab (the paper's choice for its truncated-solver runs)
+ *              or CG on the normal equations of the Schur operator.
+ *  tol         target relative residual of the full operator (FP64).
+ *  max_iter    Krylov iterations per right-hand side, all cycles included.
+ *  inner_prec  precision of the Krylov iteration.  FL_PREC_F64 runs the
+ *              whole solve in FP64; F32 runs FP32 vectors and links; BF16
+ *              stores the links in bfloat16 (FP32 vectors and arithmetic).
+ *              For F32/BF16 the FP64 residual b - Dx is recomputed and the
+ *              iteration residual replaced whenever the latter has dropped
+ *              by `delta` since the last replacement (reliable updates).
+ *  gauge_reals 18 (full links) or 12 (rows 0 and 1; row 2 rebuilt as
+ *              conj(row0 x row1)) for the F32/BF16 inner operator.
+ *  delta       reliable-update trigger in (0, 1); 0 selects 0.1.
+ *  truncated   1: low-precision (LP) solve of the truncated solver method:
+ *              inner precision only, stops when the iteration's own
+ *              residual reaches tol, no FP64 correction.  The LP map is a
+ *              deterministic function of the source, independent of the
+ *              batch it is solved in.
+ *  batch       maximum right-hand sides per device batch (0: default).
+ */
+typedef struct {
+    int solver;
+    double tol;
+    int max_iter;
+    int inner_prec;
+    int gauge_reals;
+    double delta;
+    int truncated;
+    int batch;
+} fl_solver_params;
+
+/* per right-hand side */
+typedef struct {
+    int iters;          /* Krylov iterations */
+    int updates;        /* FP64 residual replacements */
+    int converged;      /* 1 if true_resid <= tol */
+    double true_resid;  /* |D x - b| / |b| recomputed in FP64 on the full operator
+                           (truncated solves: the iteration's own estimate) */
+} fl_solver_stats;
+
+/*
+ * Stochastic estimator parameters (Eq. (loop stochastic), dilution and the
+ * truncated solver method of Sec. II):
+ *   Lhat = (1/n_lp) sum_{r in LP} sum_d eta_{r,d}^+ Gamma phi^LP_{r,d}
+ *        + (1/n_hp) sum_{r in HP} sum_d eta_{r,d}^+ Gamma (phi^HP - phi^LP)
+ * with LP noise indices r0 .. r0+n_lp-1 and HP indices following them,
+ * eta_{r,d} = P_d xi_r the diluted noise and phi = D^{-1} eta.  n_hp = 0
+ * gives the plain estimator over n_lp vectors solved with the LP params.
+ * Noise: xi_r(site, spin, colour) from the k-th output of SplitMix64
+ * (Steele, Lea, Flood 2014) started at `seed`, k = ((r V + site) 4 + spin) 3
+ * + colour; with b63, b62 its top bits, Z4: i^(2 b63 + b62); complex Z2:
+ * ((-1)^b63 + i (-1)^b62)/sqrt 2; real Z2: (-1)^b63.
+ */
+typedef struct {
+    int noise;                 /* fl_noise_kind */
+    unsigned long long seed;
+    long long r0;              /* first noise index */
+    int n_lp, n_hp;
+    int dilution;              /* FL_DIL_* mask */
+    int t_begin, t_end;        /* timeslices estimated: t_begin .. t_end-1 */
+} fl_noise_params;
+
+/* Fill p with defaults: BiCGStab, tol 1e-12, max_iter 20000, FP32 inner
+ * with 12-real links, delta 0.1, not truncated, default batch. */
+void fl_solver_params_default(fl_solver_params *p);
+
+/* Library version string. */
+const char *fl_version(void);
+
+/* Create a context for one lattice on HIP device `device`.  dims: four
+ * even extents >= 2; bc_t = +1 (periodic) or -1 (antiperiodic) in time. */
+fl_status fl_create(fl_ctx **ctx, int device, const int dims[4], int bc_t);
+
+/* Release every device buffer of the context.  NULL is accepted. */
+fl_status fl_destroy(fl_ctx *ctx);
+
+/* Stream for all later device work of the context (hipStream_t passed as
+ * void*, e.g. torch.cuda.current_stream().cuda_stream); NULL: the default
+ * stream.  Calls are asynchronous with respect to the host only where
+ * noted; every entry point below returns after its work is complete. */
+fl_status fl_set_stream(fl_ctx *ctx, void *hip_stream);
+
+/* Gauge field U (layout above), copied to the device and converted to the
+ * per-precision link layouts.  The paper's input configurations (Sec. II). */
+fl_status fl_set_gauge(fl_ctx *ctx, const double *U, fl_where where);
+
+/* Hopping parameter kappa > 0 (Sec. II). */
+fl_status fl_set_kappa(fl_ctx *ctx, double kappa);
+
+/* out = D in (dagger = 0) or D^+ in = g5 D g5 in (dagger = 1) for nrhs
+ * spinors in the canonical layout, FP64. */
+fl_status fl_apply_D(fl_ctx *ctx, const double *in, double *out, int nrhs, int dagger,
+                     fl_where where);
+
+/* Solve D x_k = b_k for nrhs right-hand sides (canonical spinor layout)
+ * to the stopping rule of Sec. III, via the Schur system
+ * x_e = (1 - k^2 H_eo H_oe)^{-1} (b_e + k H_eo b_o), x_o = b_o + k H_oe x_e.
+ * stats: NULL or an array of nrhs entries (host memory). */
+fl_status fl_solve(fl_ctx *ctx, const double *b, double *x, int nrhs,
+                   const fl_solver_params *p, fl_solver_stats *stats, fl_where where);
+
+/* Exact loops, Eq. (loop), on whole timeslices t0[0..nt-1]: 12 Vs point
+ * sources per timeslice (Sec. II).  L: [ngamma][nt][Vs][2];
+ * S: NULL or [nt][Vs][4][4][2], the colour-traced S(y)_{alpha beta} =
+ * sum_a G(y;y)_{alpha a, beta a} with L_Gamma = sum Gamma_{beta alpha} S_{alpha beta}.
+ * L and S are in `where` memory. */
+fl_status fl_loops_exact(fl_ctx *ctx, const int *t0, int nt, const int *gammas, int ngamma,
+                         const fl_solver_params *p, double *L, double *S, fl_where where);
+
+/* Exact loops at an explicit host list of lexicographic sites:
+ * L: [ngamma][nsites][2], S: NULL or [nsites][4][4][2]. */
+fl_status fl_loops_exact_sites(fl_ctx *ctx, const long long *sites, long long nsites,
+                               const int *gammas, int ngamma, const fl_solver_params *p,
+                               double *L, double *S, fl_where where);
+
+/* Stochastic / truncated-solver-method loops (fl_noise_params above).
+ * lp: solver of the first ensemble; hp: solver of the correction ensemble
+ * (ignored when n_hp = 0).  L: [ngamma][t_end-t_begin][Vs][2]. */
+fl_status fl_loops_stochastic(fl_ctx *ctx, const fl_noise_params *np, const int *gammas,
+                              int ngamma, const fl_solver_params *lp,
+                              const fl_solver_params *hp, double *L, fl_where where);
+
+/* Truncated-solver-method loops for several lattices of uneven size in one
+ * batch: every Krylov stage of all lattices runs in the same kernel launch
+ * (nctx <= 4 contexts on the same device and stream).  np[i], L[i] as in
+ * fl_loops_stochastic for context i. */
+fl_status fl_loops_stochastic_multi(fl_ctx **ctxs, int nctx, const fl_noise_params *np,
+                                    const int *gammas, int ngamma,
+                                    const fl_solver_params *lp, const fl_solver_params *hp,
+                                    double **L, fl_where where);
+
+/* Gradient of F = Re sum_{Gamma,t,xs} conj(w[Gamma][t][xs]) L_Gamma(xs,t) for the
+ * exact loops of timeslices t0 with respect to kappa and every link.
+ * w: [ngamma][nt][Vs][2]; sites whose weights are all zero are not solved.
+ * The adjoint solutions come from gamma_5-hermiticity, D^{-+} = g5 D^{-1} g5,
+ * so no solves beyond the forward point sources are needed.
+ * dU: [4][V][3][3][2] with dU = dF/dRe U + i dF/dIm U; dkappa: host double. */
+fl_status fl_loops_grad(fl_ctx *ctx, const int *t0, int nt, const int *gammas, int ngamma,
+                        const double *w, const fl_solver_params *p, double *dU,
+                        double *dkappa, fl_where where);
+
+/* Kernel timing with HIP events recorded on the context stream around every
+ * launch of the named kernel while enabled (kernel ids below).  Reset on
+ * enable.  ms: summed event time; launches: count; bytes: summed
+ * algorithmic bytes of those launches (links and spinors read once, outputs
+ * written once). */
+enum { FL_PROF_DSLASH = 0, FL_PROF_NKERNELS = 4 };
+fl_status fl_profile_enable(fl_ctx *ctx, int kernel, int enable);
+fl_status fl_profile_read(fl_ctx *ctx, int kernel, double *ms, long long *launches,
+                          double *bytes);
+
+/* Half-dslash micro-benchmark: nrep launches of the hopping kernel
+ * out_e = H_eo in_o for nrhs right-hand sides at precision `prec` and
+ * gauge_reals, cycling through `nsets` independent buffer sets (to defeat
+ * on-chip caches), timed with HIP events on the context stream.
+ * ms_per_launch and bytes_per_launch (algorithmic) are returned. */
+fl_status fl_bench_dslash(fl_ctx *ctx, int prec, int gauge_reals, int nrhs, int nrep,
+                          int nsets, double *ms_per_launch, double *bytes_per_launch);
+
+/* Text of the last error of ctx (or of the last failed fl_create when ctx
+ * is NULL). */
+const char *fl_last_error(const fl_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLOOP_H */

@@ -1,0 +1,370 @@
+"""Python binding of the MI355X loop library (include/floop.h).
+
+Disconnected fermion loops L(x) = Tr[Gamma G(x;x)] of arXiv:1108.2473
+(Eq. (loop)), exact and stochastic, computed by hand-written HIP kernels
+for gfx950.  This module only marshals arguments: every step of the
+computation runs inside libfloop.so.  Arrays are numpy (host memory) or
+torch CUDA tensors (device memory, used in place on torch's current stream).
+
+Layouts (complex128):  U[4][V][3][3], spinors [nrhs][V][4][3],
+loops [ngamma][nt][Vs].  Gamma insertions are 4-bit masks
+(Gamma = g1^b0 g2^b1 g3^b2 g4^b3; 1 -> 0, g5 -> 15).
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libfloop.so")
+
+FL_HOST, FL_DEVICE = 0, 1
+PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
+SOLVER_BICGSTAB, SOLVER_CGNR = 0, 1
+NOISE_Z4, NOISE_CZ2, NOISE_Z2 = 0, 1, 2
+DIL_TIME, DIL_SPIN, DIL_COLOUR, DIL_EVENODD, DIL_CUBIC = 1, 2, 4, 8, 16
+PROF_DSLASH = 0
+GAMMA_1, GAMMA_5 = 0, 15
+GAMMAS_PAPER = [0, 15, 1, 2, 4, 8]  # 1, g5, g1, g2, g3, g4
+
+_STATUS = {0: "FL_OK", -1: "FL_ERR_ARG", -2: "FL_ERR_STATE", -3: "FL_ERR_DEVICE", -4: "FL_ERR_NOMEM",
+           -5: "FL_ERR_NOCONV", -6: "FL_ERR_BREAKDOWN"}
+
+
+class FloopError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _SolverParams(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("inner_prec", ctypes.c_int), ("gauge_reals", ctypes.c_int), ("delta", ctypes.c_double),
+                ("truncated", ctypes.c_int), ("batch", ctypes.c_int)]
+
+
+class _SolverStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("updates", ctypes.c_int), ("converged", ctypes.c_int),
+                ("true_resid", ctypes.c_double)]
+
+
+class _NoiseParams(ctypes.Structure):
+    _fields_ = [("noise", ctypes.c_int), ("seed", ctypes.c_ulonglong), ("r0", ctypes.c_longlong),
+                ("n_lp", ctypes.c_int), ("n_hp", ctypes.c_int), ("dilution", ctypes.c_int),
+                ("t_begin", ctypes.c_int), ("t_end", ctypes.c_int)]
+
+
+@dataclass
+class SolverParams:
+    """Solver parameters (see fl_solver_params in include/floop.h)."""
+    solver: int = SOLVER_BICGSTAB
+    tol: float = 1e-12
+    max_iter: int = 20000
+    inner_prec: int = PREC_F32
+    gauge_reals: int = 12
+    delta: float = 0.1
+    truncated: bool = False
+    batch: int = 0
+
+    def c(self):
+        return _SolverParams(self.solver, self.tol, self.max_iter, self.inner_prec, self.gauge_reals,
+                             self.delta, int(self.truncated), self.batch)
+
+
+@dataclass
+class NoiseParams:
+    """Stochastic / truncated-solver estimator (see fl_noise_params)."""
+    noise: int = NOISE_Z4
+    seed: int = 0
+    r0: int = 0
+    n_lp: int = 1
+    n_hp: int = 0
+    dilution: int = DIL_TIME | DIL_SPIN | DIL_COLOUR
+    t_begin: int = 0
+    t_end: int = 1
+
+    def c(self):
+        return _NoiseParams(self.noise, self.seed & (2**64 - 1), self.r0, self.n_lp, self.n_hp,
+                            self.dilution, self.t_begin, self.t_end)
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libfloop.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FloopError(-3, f"HIP library not built: {LIB_PATH} missing (run __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname; loading it first
+    # makes libfloop bind to that copy, so torch tensors and the library share
+    # one runtime (a second runtime in the process hides the GPU from torch)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double)
+    ll = ctypes.c_longlong
+    L.fl_version.restype = ctypes.c_char_p
+    L.fl_last_error.restype = ctypes.c_char_p
+    L.fl_last_error.argtypes = [vp]
+    L.fl_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(i), i]
+    L.fl_destroy.argtypes = [vp]
+    L.fl_set_stream.argtypes = [vp, vp]
+    L.fl_set_gauge.argtypes = [vp, vp, i]
+    L.fl_set_kappa.argtypes = [vp, d]
+    L.fl_apply_D.argtypes = [vp, vp, vp, i, i, i]
+    L.fl_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(_SolverParams), ctypes.POINTER(_SolverStats), i]
+    L.fl_loops_exact.argtypes = [vp, ctypes.POINTER(i), i, ctypes.POINTER(i), i,
+                                 ctypes.POINTER(_SolverParams), vp, vp, i]
+    L.fl_loops_exact_sites.argtypes = [vp, ctypes.POINTER(ll), ll, ctypes.POINTER(i), i,
+                                       ctypes.POINTER(_SolverParams), vp, vp, i]
+    L.fl_loops_stochastic.argtypes = [vp, ctypes.POINTER(_NoiseParams), ctypes.POINTER(i), i,
+                                      ctypes.POINTER(_SolverParams), ctypes.POINTER(_SolverParams), vp, i]
+    L.fl_loops_stochastic_multi.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(_NoiseParams),
+                                            ctypes.POINTER(i), i, ctypes.POINTER(_SolverParams),
+                                            ctypes.POINTER(_SolverParams), ctypes.POINTER(vp), i]
+    L.fl_loops_grad.argtypes = [vp, ctypes.POINTER(i), i, ctypes.POINTER(i), i, vp,
+                                ctypes.POINTER(_SolverParams), vp, dp, i]
+    L.fl_profile_enable.argtypes = [vp, i, i]
+    L.fl_profile_read.argtypes = [vp, i, dp, ctypes.POINTER(ll), dp]
+    L.fl_bench_dslash.argtypes = [vp, i, i, i, i, i, dp, dp]
+    L.fl_solver_params_default.argtypes = [ctypes.POINTER(_SolverParams)]
+    for name in ("fl_create", "fl_destroy", "fl_set_stream", "fl_set_gauge", "fl_set_kappa", "fl_apply_D",
+                 "fl_solve", "fl_loops_exact", "fl_loops_exact_sites", "fl_loops_stochastic",
+                 "fl_loops_stochastic_multi", "fl_loops_grad", "fl_profile_enable", "fl_profile_read",
+                 "fl_bench_dslash"):
+        getattr(L, name).restype = i
+    _lib = L
+    return L
+
+
+def version() -> str:
+    return lib().fl_version().decode()
+
+
+def _ints(seq):
+    seq = [int(v) for v in seq]
+    return (ctypes.c_int * max(1, len(seq)))(*seq), len(seq)
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class _Arr:
+    """Pointer and location of an input array (numpy host or torch device)."""
+
+    def __init__(self, a, shape_tail=None):
+        if _is_torch(a):
+            torch = _torch()
+            if not a.is_cuda:
+                a = a.detach().numpy()
+            else:
+                if a.dtype != torch.complex128:
+                    raise TypeError("device arrays must be torch.complex128")
+                a = a.contiguous()
+                self.obj, self.ptr, self.where, self.torch = a, a.data_ptr(), FL_DEVICE, True
+                self.shape = tuple(a.shape)
+                return
+        a = np.ascontiguousarray(a, dtype=np.complex128)
+        self.obj, self.ptr, self.where, self.torch = a, a.ctypes.data, FL_HOST, False
+        self.shape = a.shape
+
+
+def _empty_like_where(ref: _Arr, shape):
+    if ref.torch:
+        torch = _torch()
+        t = torch.empty(shape, dtype=torch.complex128, device=ref.obj.device)
+        return t, t.data_ptr()
+    a = np.empty(shape, dtype=np.complex128)
+    return a, a.ctypes.data
+
+
+class Lattice:
+    """One lattice on one GPU: context of the C library (fl_ctx)."""
+
+    def __init__(self, dims, bc_t=-1, device=0):
+        self.dims = tuple(int(v) for v in dims)
+        self.V = int(np.prod(self.dims))
+        self.Vs = self.dims[0] * self.dims[1] * self.dims[2]
+        self.bc_t = bc_t
+        h = ctypes.c_void_p()
+        d = (ctypes.c_int * 4)(*self.dims)
+        st = lib().fl_create(ctypes.byref(h), device, d, bc_t)
+        if st != 0:
+            raise FloopError(st, lib().fl_last_error(None).decode())
+        self._h = h
+        self.device = device
+        self.kappa = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise FloopError(st, lib().fl_last_error(self._h).decode())
+
+    def _stream_for(self, arr: _Arr):
+        if arr.torch:
+            torch = _torch()
+            s = torch.cuda.current_stream(arr.obj.device).cuda_stream
+        else:
+            s = None
+        self._check(lib().fl_set_stream(self._h, s))
+
+    def set_stream(self, stream_ptr):
+        self._check(lib().fl_set_stream(self._h, stream_ptr))
+
+    def set_gauge(self, U):
+        a = _Arr(U)
+        if a.shape != (4, self.V, 3, 3):
+            raise ValueError(f"gauge field must have shape (4, {self.V}, 3, 3)")
+        self._stream_for(a)
+        self._check(lib().fl_set_gauge(self._h, ctypes.c_void_p(a.ptr), a.where))
+
+    def set_kappa(self, kappa):
+        self._check(lib().fl_set_kappa(self._h, float(kappa)))
+        self.kappa = float(kappa)
+
+    def _spinors(self, psi):
+        a = _Arr(psi)
+        if a.shape[-3:] != (self.V, 4, 3):
+            raise ValueError(f"spinors must have shape (..., {self.V}, 4, 3)")
+        nrhs = int(np.prod(a.shape[:-3])) if len(a.shape) > 3 else 1
+        return a, nrhs
+
+    def apply_D(self, psi, dagger=False):
+        a, nrhs = self._spinors(psi)
+        out, optr = _empty_like_where(a, a.shape)
+        self._stream_for(a)
+        self._check(lib().fl_apply_D(self._h, ctypes.c_void_p(a.ptr), ctypes.c_void_p(optr), nrhs,
+                                     int(dagger), a.where))
+        return out
+
+    def solve(self, b, params: SolverParams = None, check=True):
+        """Solve D x = b; returns (x, stats) with stats a list of dicts."""
+        params = params or SolverParams()
+        a, nrhs = self._spinors(b)
+        out, optr = _empty_like_where(a, a.shape)
+        stats = (_SolverStats * max(1, nrhs))()
+        self._stream_for(a)
+        st = lib().fl_solve(self._h, ctypes.c_void_p(a.ptr), ctypes.c_void_p(optr), nrhs,
+                            ctypes.byref(params.c()), stats, a.where)
+        if check and st not in (0,):
+            self._check(st)
+        info = [dict(iters=s.iters, updates=s.updates, converged=bool(s.converged),
+                     true_resid=s.true_resid) for s in stats[:nrhs]]
+        return out, info
+
+    def _out(self, shape, device):
+        if device:
+            torch = _torch()
+            t = torch.zeros(shape, dtype=torch.complex128, device=f"cuda:{self.device}")
+            self.set_stream(torch.cuda.current_stream(t.device).cuda_stream)
+            return t, t.data_ptr(), FL_DEVICE
+        a = np.zeros(shape, dtype=np.complex128)
+        return a, a.ctypes.data, FL_HOST
+
+    def loops_exact(self, t0, gammas, params: SolverParams = None, want_S=False, device=False):
+        """Exact loops, Eq. (loop), on whole timeslices: L [ngamma][nt][Vs] (and S)."""
+        params = params or SolverParams()
+        t_arr, nt = _ints(t0)
+        g_arr, ng = _ints(gammas)
+        L, lp, where = self._out((ng, nt, self.Vs), device)
+        S, sp = (None, None)
+        if want_S:
+            S, sp, _ = self._out((nt, self.Vs, 4, 4), device)
+        self._check(lib().fl_loops_exact(self._h, t_arr, nt, g_arr, ng, ctypes.byref(params.c()),
+                                         ctypes.c_void_p(lp), ctypes.c_void_p(sp) if want_S else None, where))
+        return (L, S) if want_S else L
+
+    def loops_exact_sites(self, sites, gammas, params: SolverParams = None, want_S=False, device=False):
+        """Exact loops at explicit lexicographic sites: L [ngamma][nsites] (and S)."""
+        params = params or SolverParams()
+        sites = np.ascontiguousarray(sites, dtype=np.int64)
+        g_arr, ng = _ints(gammas)
+        L, lp, where = self._out((ng, sites.size), device)
+        S, sp = (None, None)
+        if want_S:
+            S, sp, _ = self._out((sites.size, 4, 4), device)
+        self._check(lib().fl_loops_exact_sites(
+            self._h, sites.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), sites.size, g_arr, ng,
+            ctypes.byref(params.c()), ctypes.c_void_p(lp), ctypes.c_void_p(sp) if want_S else None, where))
+        return (L, S) if want_S else L
+
+    def loops_stochastic(self, noise: NoiseParams, gammas, lp: SolverParams = None,
+                         hp: SolverParams = None, device=False):
+        """Diluted stochastic / truncated-solver loops: L [ngamma][t_end-t_begin][Vs]."""
+        return loops_stochastic_multi([self], [noise], gammas, lp, hp, device)[0]
+
+    def loops_grad(self, t0, gammas, w, params: SolverParams = None):
+        """Gradient of F = Re sum conj(w) L_exact w.r.t. the links and kappa.
+
+        Returns (dU [4][V][3][3], dkappa) with dU = dF/dRe U + i dF/dIm U."""
+        params = params or SolverParams()
+        t_arr, nt = _ints(t0)
+        g_arr, ng = _ints(gammas)
+        a = _Arr(w)
+        if a.shape != (ng, nt, self.Vs):
+            raise ValueError(f"weights must have shape ({ng}, {nt}, {self.Vs})")
+        dU, dptr = _empty_like_where(a, (4, self.V, 3, 3))
+        dk = ctypes.c_double(0.0)
+        self._stream_for(a)
+        self._check(lib().fl_loops_grad(self._h, t_arr, nt, g_arr, ng, ctypes.c_void_p(a.ptr),
+                                        ctypes.byref(params.c()), ctypes.c_void_p(dptr), ctypes.byref(dk),
+                                        a.where))
+        return dU, dk.value
+
+    def profile_enable(self, kernel=PROF_DSLASH, on=True):
+        self._check(lib().fl_profile_enable(self._h, kernel, int(on)))
+
+    def profile_read(self, kernel=PROF_DSLASH):
+        ms, n, b = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+        self._check(lib().fl_profile_read(self._h, kernel, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return dict(ms=ms.value, launches=n.value, bytes=b.value)
+
+    def bench_dslash(self, prec=PREC_F32, gauge_reals=12, nrhs=1, nrep=100, nsets=8):
+        ms, b = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().fl_bench_dslash(self._h, prec, gauge_reals, nrhs, nrep, nsets, ctypes.byref(ms),
+                                          ctypes.byref(b)))
+        return dict(ms=ms.value, bytes=b.value)
+
+
+def loops_stochastic_multi(lattices, noises, gammas, lp: SolverParams = None, hp: SolverParams = None,
+                           device=False):
+    """Stochastic / truncated-solver loops for up to 4 lattices solved in one batch."""
+    lp = lp or SolverParams()
+    hp = hp or SolverParams()
+    n = len(lattices)
+    g_arr, ng = _ints(gammas)
+    hs = (ctypes.c_void_p * n)(*[l._h.value for l in lattices])
+    nps = (_NoiseParams * n)(*[q.c() for q in noises])
+    outs, ptrs, where = [], [], FL_HOST
+    for lat, q in zip(lattices, noises):
+        o, p, where = lat._out((ng, q.t_end - q.t_begin, lat.Vs), device)
+        outs.append(o)
+        ptrs.append(p)
+    parr = (ctypes.c_void_p * n)(*ptrs)
+    st = lib().fl_loops_stochastic_multi(hs, n, nps, g_arr, ng, ctypes.byref(lp.c()), ctypes.byref(hp.c()),
+                                         parr, where)
+    if st != 0:
+        raise FloopError(st, lib().fl_last_error(lattices[0]._h).decode())
+    return outs

@@ -1,0 +1,385 @@
+// fl_blas.hip -- vector updates, reductions and per-system scalar steps of
+// the batched Krylov solvers.
+//
+// BiCGStab (van der Vorst 1992) is run independently for every right-hand
+// side of a batch (no block method: the low-precision map of each source
+// must not depend on the rest of the batch).  The iteration is split into
+//   v = Dhat p (+ <r0, v>)      -> alpha = rho / <r0, v>
+//   s = r - alpha v
+//   t = Dhat s (+ <t, s>, |t|^2) -> omega = <t, s> / |t|^2
+//   x += alpha p + omega s, r = s - omega t (+ <r0, r>, |r|^2)
+//                               -> beta = (rho'/rho)(alpha/omega)
+//   p = r + beta (p - omega v)
+// with the operator launches in fl_dslash.hip carrying the reductions in
+// their epilogue.  Reductions are two-stage and deterministic: each
+// wavefront writes one partial per 64-site block, and one workgroup per
+// system sums the partials in a fixed order.
+#include "fl_host.h"
+
+namespace {
+
+template <typename R>
+struct Fld {
+    typedef typename SpinorFmt<R>::V V;
+    __device__ static __forceinline__ const V *cptr(const void *base, const LatGeom &g, int rhs)
+    {
+        return (const V *)base + (size_t)rhs * SpinorFmt<R>::NC * g.Vh;
+    }
+    __device__ static __forceinline__ V *ptr(void *base, const LatGeom &g, int rhs)
+    {
+        return (V *)base + (size_t)rhs * SpinorFmt<R>::NC * g.Vh;
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> cpx_of(const double *v)
+{
+    return cx<R>{(R)v[0], (R)v[1]};
+}
+
+template <typename R, int OP>
+__global__ __launch_bounds__(256) void k_blas(BlasArgs a)
+{
+    TileInfo T = tile_info(a.B);
+    if (!T.valid_rhs) return;
+    if (a.mask && !a.mask[T.sys]) return;
+    const LatGeom &g = a.B.lat[T.lat];
+    const int l = T.lat, rhs = T.rhs, i = T.site, Vh = g.Vh;
+    typedef SpinorFmt<R> F;
+    typedef SpinorFmt<double> F64;
+    R q0 = 0, q1 = 0, q2 = 0;
+    if (T.valid_site) {
+        if (OP == OP_BICG_S) {
+            const SysState &st = a.st[T.sys];
+            cx<R> al = cpx_of<R>(st.alpha);
+            cx<R> r[12], v[12];
+            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, r);
+            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, v);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) r[k] = r[k] - al * v[k];
+            F::store(Fld<R>::ptr(a.f[2][l], g, rhs), Vh, i, r);
+        } else if (OP == OP_BICG_XR) {
+            const SysState &st = a.st[T.sys];
+            cx<R> al = cpx_of<R>(st.alpha), om = cpx_of<R>(st.omega);
+            cx<R> x[12], p[12], s[12], t[12], r0[12];
+            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, x);
+            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, p);
+            F::load(Fld<R>::cptr(a.f[2][l], g, rhs), Vh, i, s);
+            F::load(Fld<R>::cptr(a.f[3][l], g, rhs), Vh, i, t);
+            F::load(Fld<R>::cptr(a.f[5][l], g, rhs), Vh, i, r0);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                x[k] = x[k] + al * p[k] + om * s[k];
+                s[k] = s[k] - om * t[k];  // new r
+                cx<R> d = cjmul(r0[k], s[k]);
+                q0 += d.re;
+                q1 += d.im;
+                q2 += s[k].re * s[k].re + s[k].im * s[k].im;
+            }
+            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, x);
+            F::store(Fld<R>::ptr(a.f[4][l], g, rhs), Vh, i, s);
+        } else if (OP == OP_BICG_P) {
+            const SysState &st = a.st[T.sys];
+            cx<R> be = cpx_of<R>(st.beta), om = cpx_of<R>(st.omega);
+            cx<R> p[12], r[12], v[12];
+            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, p);
+            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, r);
+            F::load(Fld<R>::cptr(a.f[2][l], g, rhs), Vh, i, v);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) p[k] = r[k] + be * (p[k] - om * v[k]);
+            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, p);
+        } else if (OP == OP_HI_TO_LO) {
+            cx<double> h[12];
+            cx<R> lo[12], r0[12];
+            F64::load(Fld<double>::cptr(a.f[1][l], g, rhs), Vh, i, h);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) lo[k] = cx<R>{(R)h[k].re, (R)h[k].im};
+            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, lo);
+            if (a.flag) {
+                F::store(Fld<R>::ptr(a.f[2][l], g, rhs), Vh, i, lo);
+                F::store(Fld<R>::ptr(a.f[3][l], g, rhs), Vh, i, lo);
+                cx<R> z[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) z[k] = cx<R>{(R)0, (R)0};
+                F::store(Fld<R>::ptr(a.f[4][l], g, rhs), Vh, i, z);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) r0[k] = lo[k];
+            } else {
+                F::load(Fld<R>::cptr(a.f[2][l], g, rhs), Vh, i, r0);
+            }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                cx<R> d = cjmul(r0[k], lo[k]);
+                q0 += d.re;
+                q1 += d.im;
+                q2 += lo[k].re * lo[k].re + lo[k].im * lo[k].im;
+            }
+        } else if (OP == OP_ACC_HI) {
+            cx<double> h[12];
+            cx<R> lo[12];
+            F64::load(Fld<double>::cptr(a.f[0][l], g, rhs), Vh, i, h);
+            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, lo);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) h[k] = h[k] + cx<double>{(double)lo[k].re, (double)lo[k].im};
+            F64::store(Fld<double>::ptr(a.f[0][l], g, rhs), Vh, i, h);
+            if (a.flag) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) lo[k] = cx<R>{(R)0, (R)0};
+                F::store(Fld<R>::ptr(a.f[1][l], g, rhs), Vh, i, lo);
+            }
+        } else if (OP == OP_SUB_HI) {
+            cx<double> u[12], w[12];
+            F64::load(Fld<double>::cptr(a.f[1][l], g, rhs), Vh, i, u);
+            F64::load(Fld<double>::cptr(a.f[2][l], g, rhs), Vh, i, w);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) u[k] = u[k] - w[k];
+            F64::store(Fld<double>::ptr(a.f[0][l], g, rhs), Vh, i, u);
+        } else if (OP == OP_NORM) {
+            cx<R> f[12];
+            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, f);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) q2 += f[k].re * f[k].re + f[k].im * f[k].im;
+        } else if (OP == OP_ZERO) {
+            cx<R> z[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) z[k] = cx<R>{(R)0, (R)0};
+            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, z);
+        } else if (OP == OP_CG_XR) {
+            const R al = (R)a.st[T.sys].alpha[0];
+            cx<R> x[12], r[12], p[12], q[12];
+            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, x);
+            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, r);
+            F::load(Fld<R>::cptr(a.f[2][l], g, rhs), Vh, i, p);
+            F::load(Fld<R>::cptr(a.f[3][l], g, rhs), Vh, i, q);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                x[k] = x[k] + al * p[k];
+                r[k] = r[k] - al * q[k];
+                q2 += r[k].re * r[k].re + r[k].im * r[k].im;
+            }
+            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, x);
+            F::store(Fld<R>::ptr(a.f[1][l], g, rhs), Vh, i, r);
+        } else if (OP == OP_CG_P) {
+            const R be = (R)a.st[T.sys].beta[0];
+            cx<R> p[12], z[12];
+            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, p);
+            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, z);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) p[k] = z[k] + be * p[k];
+            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, p);
+        }
+    }
+    if (OP == OP_BICG_XR || OP == OP_HI_TO_LO || OP == OP_NORM || OP == OP_CG_XR) {
+        double s0 = wave_sum((double)q0), s1 = wave_sum((double)q1), s2 = wave_sum((double)q2);
+        if (threadIdx.x % FL_WAVE == 0) {
+            const int ns = a.nsys, nb = a.B.nsb_max;
+            if (OP == OP_BICG_XR || OP == OP_HI_TO_LO) {
+                a.partial[pidx(a.slot0, ns, T.sys, nb, T.sb)] = s0;
+                a.partial[pidx(a.slot0 + 1, ns, T.sys, nb, T.sb)] = s1;
+            }
+            a.partial[pidx(a.slot0 + 2, ns, T.sys, nb, T.sb)] = s2;
+        }
+    }
+}
+
+template <typename R>
+void dispatch(const BlasArgs &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (a.op) {
+    case OP_BICG_S: hipLaunchKernelGGL((k_blas<R, OP_BICG_S>), grid, block, 0, s, a); break;
+    case OP_BICG_XR: hipLaunchKernelGGL((k_blas<R, OP_BICG_XR>), grid, block, 0, s, a); break;
+    case OP_BICG_P: hipLaunchKernelGGL((k_blas<R, OP_BICG_P>), grid, block, 0, s, a); break;
+    case OP_HI_TO_LO: hipLaunchKernelGGL((k_blas<R, OP_HI_TO_LO>), grid, block, 0, s, a); break;
+    case OP_ACC_HI: hipLaunchKernelGGL((k_blas<R, OP_ACC_HI>), grid, block, 0, s, a); break;
+    case OP_SUB_HI: hipLaunchKernelGGL((k_blas<R, OP_SUB_HI>), grid, block, 0, s, a); break;
+    case OP_NORM: hipLaunchKernelGGL((k_blas<R, OP_NORM>), grid, block, 0, s, a); break;
+    case OP_ZERO: hipLaunchKernelGGL((k_blas<R, OP_ZERO>), grid, block, 0, s, a); break;
+    case OP_CG_XR: hipLaunchKernelGGL((k_blas<R, OP_CG_XR>), grid, block, 0, s, a); break;
+    case OP_CG_P: hipLaunchKernelGGL((k_blas<R, OP_CG_P>), grid, block, 0, s, a); break;
+    default: break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-system scalar steps: one workgroup per system sums the partials of
+// the six slots in a fixed order, then lane 0 advances the recurrence
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool finite_d(double v) { return v == v && v - v == 0.0; }
+
+__global__ __launch_bounds__(256) void k_scal(ScalArgs a)
+{
+    const int sys = blockIdx.x;
+    if (a.mask) {
+        if (!a.mask[sys]) return;
+    } else if (!a.active[sys]) {
+        return;
+    }
+    int l = 0;
+    for (int k = 1; k < FL_MAXLAT; ++k)
+        if (k < a.B.nlat && sys >= a.B.lat[k].sys0) l = k;
+    const int nsb = a.B.lat[l].nsb, nb = a.B.nsb_max;
+    __shared__ double red[6][256];
+    for (int slot = 0; slot < 6; ++slot) {
+        double acc = 0;
+        for (int sb = threadIdx.x; sb < nsb; sb += 256) acc += a.partial[pidx(slot, a.nsys, sys, nb, sb)];
+        red[slot][threadIdx.x] = acc;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int slot = 0; slot < 6; ++slot) red[slot][threadIdx.x] += red[slot][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double P[6];
+    for (int slot = 0; slot < 6; ++slot) P[slot] = red[slot][0];
+    SysState &s = a.st[sys];
+    switch (a.step) {
+    case SC_ALPHA: {
+        double den = P[0] * P[0] + P[1] * P[1];
+        if (!(den > 0) || !finite_d(den)) {
+            s.flags |= ST_BREAK;
+            a.active[sys] = 0;
+            break;
+        }
+        // alpha = rho / r0v
+        s.alpha[0] = (s.rho[0] * P[0] + s.rho[1] * P[1]) / den;
+        s.alpha[1] = (s.rho[1] * P[0] - s.rho[0] * P[1]) / den;
+        break;
+    }
+    case SC_OMEGA: {
+        double tt = P[2];
+        if (tt > 0 && finite_d(tt)) {
+            s.omega[0] = P[0] / tt;
+            s.omega[1] = P[1] / tt;
+        } else if (tt == 0) {
+            s.omega[0] = s.omega[1] = 0;
+        } else {
+            s.flags |= ST_BREAK;
+            a.active[sys] = 0;
+        }
+        break;
+    }
+    case SC_BETA: {
+        double rho_n[2] = {P[0], P[1]};
+        double rr = P[2];
+        s.iter += 1;
+        if (!finite_d(rr) || !finite_d(rho_n[0]) || !finite_d(rho_n[1])) {
+            s.flags |= ST_BREAK;
+            a.active[sys] = 0;
+            break;
+        }
+        s.rr = rr;
+        if (rr > s.rmax2) s.rmax2 = rr;
+        if (rr < s.delta2 * s.rmax2) s.flags |= ST_WANT_UPD;
+        if (rr <= s.stop2) {
+            s.flags |= ST_CONV_ITER;
+            a.active[sys] = 0;
+        } else if (s.iter >= s.max_iter) {
+            s.flags |= ST_MAXIT;
+            a.active[sys] = 0;
+        }
+        double om2 = s.omega[0] * s.omega[0] + s.omega[1] * s.omega[1];
+        double rh2 = s.rho[0] * s.rho[0] + s.rho[1] * s.rho[1];
+        if (a.active[sys] && (!(om2 > 0) || !(rh2 > 0))) {
+            s.flags |= ST_BREAK;
+            a.active[sys] = 0;
+        }
+        if (om2 > 0 && rh2 > 0) {
+            // beta = (rho_n / rho) * (alpha / omega)
+            double q[2] = {(rho_n[0] * s.rho[0] + rho_n[1] * s.rho[1]) / rh2,
+                           (rho_n[1] * s.rho[0] - rho_n[0] * s.rho[1]) / rh2};
+            double w[2] = {(s.alpha[0] * s.omega[0] + s.alpha[1] * s.omega[1]) / om2,
+                           (s.alpha[1] * s.omega[0] - s.alpha[0] * s.omega[1]) / om2};
+            s.beta[0] = q[0] * w[0] - q[1] * w[1];
+            s.beta[1] = q[0] * w[1] + q[1] * w[0];
+        }
+        s.rho[0] = rho_n[0];
+        s.rho[1] = rho_n[1];
+        break;
+    }
+    case SC_RESET:
+        s.tr2 = P[2];
+        s.rho[0] = P[3];
+        s.rho[1] = P[4];
+        s.rr = P[5];
+        s.rmax2 = P[5];
+        s.flags &= ~(ST_CONV_ITER | ST_WANT_UPD);
+        break;
+    case SC_INIT:
+        s.rho[0] = P[3];
+        s.rho[1] = P[4];
+        s.rr = P[5];
+        s.rmax2 = P[5];
+        s.flags = 0;
+        s.alpha[0] = s.omega[0] = 1;
+        s.alpha[1] = s.omega[1] = 0;
+        s.beta[0] = s.beta[1] = 0;
+        if (P[5] <= s.stop2) {
+            s.flags |= ST_CONV_ITER;
+            a.active[sys] = 0;
+        } else {
+            a.active[sys] = 1;
+        }
+        break;
+    case SC_CG_INIT:  // slot 2: |z|^2 with z = Dhat^+ r; slot 5: |r|^2
+        s.zz = P[2];
+        s.rr = P[5];
+        s.beta[0] = s.beta[1] = 0;
+        s.flags &= ST_MAXIT;
+        if (P[5] <= s.stop2 || !(P[2] > 0)) {
+            s.flags |= ST_CONV_ITER;
+            a.active[sys] = 0;
+        } else {
+            a.active[sys] = 1;
+        }
+        break;
+    case SC_CG_ALPHA:  // slot 2: |q|^2 with q = Dhat p
+        if (!(P[2] > 0) || !finite_d(P[2])) {
+            s.flags |= ST_BREAK;
+            a.active[sys] = 0;
+        } else {
+            s.alpha[0] = s.zz / P[2];
+        }
+        break;
+    case SC_CG_BETA: {  // slot 2: |z'|^2, slot 5: |r|^2
+        double zn = P[2], rr = P[5];
+        s.iter += 1;
+        s.rr = rr;
+        if (!finite_d(zn) || !finite_d(rr)) {
+            s.flags |= ST_BREAK;
+            a.active[sys] = 0;
+            break;
+        }
+        s.beta[0] = zn / s.zz;
+        s.zz = zn;
+        if (rr <= s.stop2) {
+            s.flags |= ST_CONV_ITER;
+            a.active[sys] = 0;
+        } else if (s.iter >= s.max_iter) {
+            s.flags |= ST_MAXIT;
+            a.active[sys] = 0;
+        }
+        break;
+    }
+    default: break;
+    }
+}
+
+}  // namespace
+
+void launch_blas(bool fp64, const BlasArgs &a, hipStream_t s)
+{
+    if (a.B.ntiles == 0) return;
+    dim3 grid(a.B.ntiles), block(FL_WAVE * a.B.RT);
+    if (fp64)
+        dispatch<double>(a, grid, block, s);
+    else
+        dispatch<float>(a, grid, block, s);
+}
+
+void launch_scalars(const ScalArgs &a, hipStream_t s)
+{
+    if (a.nsys == 0) return;
+    hipLaunchKernelGGL(k_scal, dim3(a.nsys), dim3(256), 0, s, a);
+}

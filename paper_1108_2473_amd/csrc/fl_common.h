@@ -1,0 +1,320 @@
+// fl_common.h -- device-side types shared by the HIP kernels of the loop
+// library: complex arithmetic, spinor and link storage formats, the
+// checkerboard geometry, the multi-lattice tile map and wave reductions.
+//
+// Data layout in HBM (per lattice, per parity, structure of arrays):
+//   spinor field of one right-hand side: NC vectors x Vh sites, vector c of
+//     site i at base[c*Vh + i]; consecutive right-hand sides follow each
+//     other (stride NC*Vh vectors).  FP64: 12 x double2, FP32: 6 x float4.
+//   links: [mu][parity][NCg][Vh] vectors.  FP64 18 reals: 9 x double2;
+//     FP32 12 reals: 3 x float4 (rows 0 and 1); FP32 18 reals: 9 x float2;
+//     BF16 12 reals: 3 x (4 bf16).  Row 2 of a 12-real link is rebuilt as
+//     conj(row0 x row1), exact for SU(3).
+// Each wavefront (64 lanes) works on 64 consecutive checkerboard sites of
+// ONE right-hand side, so per-RHS masks and reductions are wave-uniform and
+// every reduction partial covers a fixed block of 64 sites, whatever the
+// batch composition.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FL_MAXLAT 4
+#define FL_WAVE 64
+
+// ---------------------------------------------------------------------------
+// complex numbers
+// ---------------------------------------------------------------------------
+template <typename R>
+struct cx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return cx<R>{a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return cx<R>{a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a) { return cx<R>{-a.re, -a.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b)
+{
+    return cx<R>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return cx<R>{s * a.re, s * a.im}; }
+// i * a
+template <typename R>
+__device__ __forceinline__ cx<R> ti(cx<R> a) { return cx<R>{-a.im, a.re}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cj(cx<R> a) { return cx<R>{a.re, -a.im}; }
+// conj(a) * b
+template <typename R>
+__device__ __forceinline__ cx<R> cjmul(cx<R> a, cx<R> b)
+{
+    return cx<R>{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+
+// ---------------------------------------------------------------------------
+// spinor storage: 24 reals (spin-major, colour, re/im) per site
+// ---------------------------------------------------------------------------
+template <typename R>
+struct SpinorFmt;
+
+template <>
+struct SpinorFmt<double> {
+    typedef double2 V;
+    static constexpr int NC = 12;
+    __device__ static __forceinline__ void load(const V *__restrict__ f, int Vh, int i, cx<double> s[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            V v = f[(size_t)c * Vh + i];
+            s[c] = cx<double>{v.x, v.y};
+        }
+    }
+    __device__ static __forceinline__ void store(V *__restrict__ f, int Vh, int i, const cx<double> s[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) f[(size_t)c * Vh + i] = make_double2(s[c].re, s[c].im);
+    }
+};
+
+template <>
+struct SpinorFmt<float> {
+    typedef float4 V;
+    static constexpr int NC = 6;
+    __device__ static __forceinline__ void load(const V *__restrict__ f, int Vh, int i, cx<float> s[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            V v = f[(size_t)c * Vh + i];
+            s[2 * c] = cx<float>{v.x, v.y};
+            s[2 * c + 1] = cx<float>{v.z, v.w};
+        }
+    }
+    __device__ static __forceinline__ void store(V *__restrict__ f, int Vh, int i, const cx<float> s[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            f[(size_t)c * Vh + i] = make_float4(s[2 * c].re, s[2 * c].im, s[2 * c + 1].re, s[2 * c + 1].im);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// bfloat16: round-to-nearest-even from fp32 (the top 16 bits of the fp32
+// pattern after adding half an ulp of the kept part, ties to even)
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    union {
+        float f;
+        uint32_t u;
+    } v;
+    v.f = f;
+    if ((v.u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((v.u >> 16) | ((v.u & 0xffffu) ? 0x40u : 0u));
+    uint32_t lsb = (v.u >> 16) & 1u;
+    v.u += 0x7fffu + lsb;
+    return (uint16_t)(v.u >> 16);
+}
+
+__host__ __device__ __forceinline__ float bf16_to_f32(uint32_t h)
+{
+    union {
+        float f;
+        uint32_t u;
+    } v;
+    v.u = h << 16;
+    return v.f;
+}
+
+// ---------------------------------------------------------------------------
+// link storage formats
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void rebuild_row2(cx<R> U[3][3])
+{
+    // row2 = conj(row0 x row1)
+    U[2][0] = cj(U[0][1] * U[1][2] - U[0][2] * U[1][1]);
+    U[2][1] = cj(U[0][2] * U[1][0] - U[0][0] * U[1][2]);
+    U[2][2] = cj(U[0][0] * U[1][1] - U[0][1] * U[1][0]);
+}
+
+struct LinkF64R18 {
+    typedef double R;
+    typedef double2 V;
+    static constexpr int NC = 9;
+    static constexpr int REALS = 18;
+    static constexpr int BYTES = 144;
+    __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<double> U[3][3])
+    {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            V v = g[(size_t)c * Vh + i];
+            U[c / 3][c % 3] = cx<double>{v.x, v.y};
+        }
+    }
+};
+
+struct LinkF32R18 {
+    typedef float R;
+    typedef float2 V;
+    static constexpr int NC = 9;
+    static constexpr int REALS = 18;
+    static constexpr int BYTES = 72;
+    __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<float> U[3][3])
+    {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            V v = g[(size_t)c * Vh + i];
+            U[c / 3][c % 3] = cx<float>{v.x, v.y};
+        }
+    }
+};
+
+struct LinkF32R12 {
+    typedef float R;
+    typedef float4 V;
+    static constexpr int NC = 3;
+    static constexpr int REALS = 12;
+    static constexpr int BYTES = 48;
+    __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<float> U[3][3])
+    {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            V v = g[(size_t)c * Vh + i];
+            int e = 2 * c;  // complex entries 2c, 2c+1 of rows 0..1
+            U[e / 3][e % 3] = cx<float>{v.x, v.y};
+            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{v.z, v.w};
+        }
+        rebuild_row2(U);
+    }
+};
+
+struct LinkBF16R12 {
+    typedef float R;
+    typedef uint2 V;  // four bf16 values
+    static constexpr int NC = 3;
+    static constexpr int REALS = 12;
+    static constexpr int BYTES = 24;
+    __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<float> U[3][3])
+    {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            V v = g[(size_t)c * Vh + i];
+            int e = 2 * c;
+            U[e / 3][e % 3] = cx<float>{bf16_to_f32(v.x & 0xffffu), bf16_to_f32(v.x >> 16)};
+            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{bf16_to_f32(v.y & 0xffffu), bf16_to_f32(v.y >> 16)};
+        }
+        rebuild_row2(U);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// geometry of a batch of lattices and the tile map
+// ---------------------------------------------------------------------------
+struct LatGeom {
+    int L[4];     // extents x, y, z, t
+    int Lh0;      // Lx / 2
+    int Vh;       // sites per parity
+    int bc_t;     // +1 or -1
+    int nsb;      // 64-site blocks per parity: ceil(Vh / 64)
+    int nrhs;     // right-hand sides of this lattice in the batch
+    int sys0;     // index of its first right-hand side in per-system arrays
+    int tile0;    // first tile of this lattice in the flat grid
+    int nrb;      // right-hand-side blocks: ceil(nrhs / RT)
+};
+
+struct BatchGeom {
+    int nlat;
+    int ntiles;
+    int RT;       // right-hand sides (wavefronts) per workgroup
+    int nsb_max;  // stride of per-system partial arrays
+    LatGeom lat[FL_MAXLAT];
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip (block b
+// runs on XCD b % 8).  Renumber them so that each XCD receives a contiguous
+// range of tiles: neighbouring sites and the right-hand sides of one site
+// block then share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int nx = 8;
+    int x = b % nx, k = b / nx;
+    int q = n / nx, r = n % nx;
+    return x * q + (x < r ? x : r) + k;
+}
+
+struct TileInfo {
+    int lat;   // lattice index in the batch
+    int sb;    // site block
+    int rhs;   // right-hand side within the lattice (this wave's)
+    int sys;   // global system index
+    int site;  // checkerboard site of this lane
+    bool valid_rhs;
+    bool valid_site;
+};
+
+__device__ __forceinline__ TileInfo tile_info(const BatchGeom &B)
+{
+    int tile = xcd_tile(blockIdx.x, gridDim.x);
+    int l = 0;
+#pragma unroll
+    for (int k = 1; k < FL_MAXLAT; ++k)
+        if (k < B.nlat && tile >= B.lat[k].tile0) l = k;
+    const LatGeom &g = B.lat[l];
+    int local = tile - g.tile0;
+    int sb = local / g.nrb;
+    int rb = local - sb * g.nrb;
+    int wave = threadIdx.x / FL_WAVE;
+    int lane = threadIdx.x % FL_WAVE;
+    TileInfo t;
+    t.lat = l;
+    t.sb = sb;
+    t.rhs = rb * B.RT + wave;
+    t.sys = g.sys0 + t.rhs;
+    t.site = sb * FL_WAVE + lane;
+    t.valid_rhs = t.rhs < g.nrhs;
+    t.valid_site = t.site < g.Vh;
+    return t;
+}
+
+// coordinates of checkerboard site i of parity p
+struct Coord {
+    int x, y, z, t;
+    int rest;  // y + Ly*(z + Lz*t)
+};
+
+__device__ __forceinline__ Coord cb_coords(const LatGeom &g, int p, int i)
+{
+    Coord c;
+    int xh = i % g.Lh0;
+    c.rest = i / g.Lh0;
+    int r = c.rest;
+    c.y = r % g.L[1];
+    r /= g.L[1];
+    c.z = r % g.L[2];
+    c.t = r / g.L[2];
+    c.x = 2 * xh + ((p + c.y + c.z + c.t) & 1);
+    return c;
+}
+
+__device__ __forceinline__ int cb_index(const LatGeom &g, int x, int y, int z, int t)
+{
+    return (x >> 1) + g.Lh0 * (y + g.L[1] * (z + g.L[2] * t));
+}
+
+// wave-wide sums in a fixed butterfly order (deterministic)
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, FL_WAVE);
+    return v;
+}
+
+// per-system partial sums: partial[(slot * nsys + sys) * nsb_max + sb]
+__device__ __forceinline__ size_t pidx(int slot, int nsys, int sys, int nsb_max, int sb)
+{
+    return ((size_t)slot * nsys + sys) * nsb_max + sb;
+}

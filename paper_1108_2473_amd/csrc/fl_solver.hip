@@ -1,0 +1,458 @@
+// fl_solver.hip -- batched even-odd Schur solves.
+//
+// Every right-hand side of every lattice in the batch runs its own Krylov
+// recurrence (BiCGStab, or CG on the normal equations of the Schur
+// operator Dhat = 1 - kappa^2 H_eo H_oe); all of them advance together, one
+// kernel launch per stage covering the whole batch, with per-system scalars
+// kept on the device.  The host looks at the per-system state every few
+// iterations only.
+//
+// Precision: the iteration runs in FP64, or in FP32 vectors with FP32 or
+// bfloat16 links.  In the low-precision modes the solution is accumulated
+// in FP64 and the FP64 residual bhat - Dhat x is recomputed, replacing the
+// iteration's residual, whenever the latter has dropped by `delta` since the
+// previous replacement and when the iteration believes it has converged
+// (reliable updates; van der Vorst and Ye 2000 on residual replacement).
+// A system is finished only when that FP64 residual meets the stopping rule
+// |D x - b| <= tol |b| of the paper (Sec. III; for the Schur system the full
+// residual equals the even-site residual).  Truncated (LP) solves stop on
+// the low-precision iteration's own residual, with no FP64 step.
+#include <cmath>
+#include <cstring>
+
+#include "fl_host.h"
+
+namespace {
+
+struct MF {  // one field per lattice
+    void *p[FL_MAXLAT] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+struct Solver {
+    SolveBatch &sb;
+    const fl_solver_params &prm;
+    BatchGeom B;
+    int nsys = 0;
+    LinkFormat fmt;
+    bool lo64;  // iteration vectors in FP64
+    hipStream_t st;
+    fl_ctx *c0;
+    MF RH, T64, R, R0, P, V, S, T, XL, TMP, XH, BH;
+    const void *gauge_lo[FL_MAXLAT], *gauge_hi[FL_MAXLAT];
+    double kap2[FL_MAXLAT];
+    double *partial = nullptr;
+    SysState *dst = nullptr;
+    int *active = nullptr, *mask = nullptr;
+    std::vector<SysState> hst;
+    std::vector<int> hact, hmask;
+    std::vector<long long> active_count;  // per lattice, at the last check
+
+    Solver(SolveBatch &b, const fl_solver_params &p) : sb(b), prm(p) {}
+
+    double lo_bytes_per_site_rhs() const { return lo64 ? 192.0 : 96.0; }
+
+    void dslash(LinkFormat f, bool lo, int par, const MF &in, const MF &out, const MF *x, const MF *y,
+                double ca, const double *cbv, int epi, int slot0, const int *msk, bool dag, bool prof)
+    {
+        DslashArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.B = B;
+        a.par = par;
+        a.slot0 = slot0;
+        a.nsys = nsys;
+        a.mask = msk;
+        a.partial = partial;
+        for (int l = 0; l < B.nlat; ++l) {
+            a.in[l] = in.p[l];
+            a.out[l] = out.p[l];
+            a.x[l] = x ? x->p[l] : nullptr;
+            a.y[l] = y ? y->p[l] : nullptr;
+            a.gauge[l] = lo ? gauge_lo[l] : gauge_hi[l];
+            a.ca[l] = ca;
+            a.cb[l] = cbv ? cbv[l] : 1.0;
+        }
+        if (prof) prof_begin(c0, FL_PROF_DSLASH);
+        launch_dslash(f, a, dag, epi, st);
+        if (prof) prof_end(c0, FL_PROF_DSLASH, 0.0);
+    }
+
+    void blas(bool fp64, int op, std::initializer_list<const MF *> fields, int flag, int slot0, const int *msk)
+    {
+        BlasArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.B = B;
+        a.op = op;
+        a.flag = flag;
+        a.slot0 = slot0;
+        a.nsys = nsys;
+        a.mask = msk;
+        a.partial = partial;
+        a.st = dst;
+        int k = 0;
+        for (const MF *f : fields) {
+            for (int l = 0; l < B.nlat; ++l) a.f[k][l] = f->p[l];
+            ++k;
+        }
+        launch_blas(fp64, a, st);
+    }
+
+    void scal(int step, const int *msk)
+    {
+        ScalArgs a;
+        a.B = B;
+        a.step = step;
+        a.nsys = nsys;
+        a.active = active;
+        a.mask = msk;
+        a.partial = partial;
+        a.st = dst;
+        launch_scalars(a, st);
+    }
+
+    double neg_k2[FL_MAXLAT], pos_k2[FL_MAXLAT];
+
+    // Dhat (or Dhat^+) applied in the iteration precision: out = in - k^2 H_eo H_oe in
+    void schur_lo(const MF &in, const MF &out, int epi_extra, const MF *y, int slot0, bool dag)
+    {
+        dslash(fmt, true, 1, in, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, dag, !dag);
+        dslash(fmt, true, 0, TMP, out, &in, y, 1.0, neg_k2, EPI_XPAY | epi_extra, slot0, active, dag, false);
+    }
+
+    // one BiCGStab iteration for every active system
+    void bicg_iteration()
+    {
+        const bool f64 = lo64;
+        schur_lo(P, V, EPI_DOTY, &R0, 0, false);                   // v = Dhat p, <r0, v>
+        scal(SC_ALPHA, nullptr);
+        blas(f64, OP_BICG_S, {&R, &V, &S}, 0, 0, active);          // s = r - alpha v
+        schur_lo(S, T, EPI_DOTX_NORM, nullptr, 0, false);           // t = Dhat s, <t, s>, |t|^2
+        scal(SC_OMEGA, nullptr);
+        blas(f64, OP_BICG_XR, {&XL, &P, &S, &T, &R, &R0}, 0, 0, active);
+        scal(SC_BETA, nullptr);
+        blas(f64, OP_BICG_P, {&P, &R, &V}, 0, 0, active);          // p = r + beta (p - omega v)
+    }
+
+    // CGNR on the Schur system: p, q = Dhat p, z = Dhat^+ r
+    void cg_iteration()
+    {
+        const bool f64 = lo64;
+        // q = Dhat p with |q|^2 (slot 2)
+        dslash(fmt, true, 1, P, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, false, true);
+        dslash(fmt, true, 0, TMP, V, &P, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, false, false);
+        scal(SC_CG_ALPHA, nullptr);
+        blas(f64, OP_CG_XR, {&XL, &R, &P, &V}, 0, 3, active);      // |r|^2 -> slot 5
+        // z = Dhat^+ r with |z|^2 (slot 2)
+        dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, true, false);
+        dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, true, false);
+        scal(SC_CG_BETA, nullptr);
+        blas(f64, OP_CG_P, {&P, &S}, 0, 0, active);
+    }
+
+    // FP64 residual of the masked systems: rh = bh - Dhat xh (|rh|^2 -> slot 2),
+    // then the iteration residual r = lo(rh) with <r0, r>, |r|^2 (slots 3..5);
+    // init = 1 also restarts the recurrence (r0 = p = r, xl = 0)
+    void replace_residual(const int *msk, int init)
+    {
+        blas(lo64, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                // xh += xl, xl = 0
+        blas(true, OP_SUB_HI, {&RH, &BH, &XH}, 0, 0, msk);           // rh = bh - xh
+        dslash(LINK_F64_R18, false, 1, XH, T64, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, false, false);
+        dslash(LINK_F64_R18, false, 0, T64, RH, &RH, nullptr, 1.0, pos_k2, EPI_XPAY | EPI_NORM, 0, msk, false,
+               false);
+        blas(lo64, OP_HI_TO_LO, {&R, &RH, &R0, &P, &XL}, init, 3, msk);
+    }
+
+    fl_status run(std::vector<SysResult> &res);
+};
+
+fl_status Solver::run(std::vector<SysResult> &res)
+{
+    c0 = sb.ctx[0];
+    st = c0->stream;
+    const int solver = prm.solver;
+    if (prm.inner_prec == FL_PREC_F64) {
+        fmt = LINK_F64_R18;
+    } else if (prm.inner_prec == FL_PREC_F32) {
+        fmt = prm.gauge_reals == 18 ? LINK_F32_R18 : LINK_F32_R12;
+    } else {
+        fmt = LINK_BF16_R12;
+    }
+    lo64 = fmt == LINK_F64_R18;
+    if (fmt == LINK_F32_R12 || fmt == LINK_BF16_R12)
+        for (int l = 0; l < sb.nlat; ++l)
+            if (!sb.ctx[l]->su3)
+                return set_err(c0, FL_ERR_ARG, "12-real link storage needs SU(3) links; use gauge_reals = 18");
+    int minr = 1 << 30;
+    for (int l = 0; l < sb.nlat; ++l) minr = std::min(minr, std::max(1, sb.nrhs[l]));
+    const int RT = minr >= 4 ? 4 : (minr >= 2 ? 2 : 1);
+    B = batch_geom(sb.ctx, sb.nrhs, sb.nlat, RT);
+    nsys = 0;
+    for (int l = 0; l < sb.nlat; ++l) nsys += sb.nrhs[l];
+    if (nsys == 0) return FL_OK;
+    if ((int)sb.bnorm.size() != nsys) return set_err(c0, FL_ERR_ARG, "internal: bnorm size");
+
+    // workspace
+    const size_t lob = lo64 ? 192 : 96;
+    for (int l = 0; l < sb.nlat; ++l) {
+        fl_ctx *c = sb.ctx[l];
+        size_t n = (size_t)sb.nrhs[l] * c->Vh;
+        RH.p[l] = ws_get(c, WS_RH, n * 192);
+        T64.p[l] = ws_get(c, WS_T64, n * 192);
+        R.p[l] = ws_get(c, WS_R, n * lob);
+        R0.p[l] = ws_get(c, WS_R0, n * lob);
+        P.p[l] = ws_get(c, WS_P, n * lob);
+        V.p[l] = ws_get(c, WS_V, n * lob);
+        S.p[l] = ws_get(c, WS_S, n * lob);
+        T.p[l] = ws_get(c, WS_T, n * lob);
+        XL.p[l] = ws_get(c, WS_XL, n * lob);
+        TMP.p[l] = ws_get(c, WS_TMP, n * lob);
+        XH.p[l] = sb.xh[l];
+        BH.p[l] = (void *)sb.bh[l];
+        for (void *q : {RH.p[l], T64.p[l], R.p[l], R0.p[l], P.p[l], V.p[l], S.p[l], T.p[l], XL.p[l], TMP.p[l]})
+            if (!q) return set_err(c, FL_ERR_NOMEM, "device allocation failed (solver vectors)");
+        gauge_lo[l] = links(c, fmt);
+        gauge_hi[l] = links(c, LINK_F64_R18);
+        if (!gauge_lo[l] || !gauge_hi[l]) return set_err(c, FL_ERR_NOMEM, "device allocation failed (links)");
+        neg_k2[l] = -c->kappa * c->kappa;
+        pos_k2[l] = c->kappa * c->kappa;
+    }
+    partial = (double *)ws_get(c0, WS_PART, sizeof(double) * 6 * (size_t)nsys * B.nsb_max);
+    dst = (SysState *)ws_get(c0, WS_STATE, sizeof(SysState) * nsys);
+    active = (int *)ws_get(c0, WS_ACTIVE, sizeof(int) * nsys);
+    mask = (int *)ws_get(c0, WS_MASK, sizeof(int) * nsys);
+    if (!partial || !dst || !active || !mask) return set_err(c0, FL_ERR_NOMEM, "device allocation failed");
+    fl_status e;
+    if ((e = hip_check(c0, hipMemsetAsync(partial, 0, sizeof(double) * 6 * (size_t)nsys * B.nsb_max, st),
+                       "memset")))
+        return e;
+
+    // initial state
+    const double tol = prm.tol;
+    const bool trunc = prm.truncated != 0;
+    double delta = prm.delta > 0 && prm.delta < 1 ? prm.delta : 0.1;
+    hst.assign(nsys, SysState());
+    for (int k = 0; k < nsys; ++k) {
+        SysState &s = hst[k];
+        std::memset(&s, 0, sizeof(s));
+        double bn = sb.bnorm[k];
+        s.tstop2 = (tol * bn) * (tol * bn);
+        // the iteration aims a little below the target so that the FP64 check passes
+        s.stop2 = trunc ? s.tstop2 : 0.25 * s.tstop2;
+        s.delta2 = (lo64 || trunc) ? 0.0 : delta * delta;
+        s.max_iter = prm.max_iter > 0 ? prm.max_iter : 20000;
+    }
+    if ((e = hip_check(c0, hipMemcpyAsync(dst, hst.data(), sizeof(SysState) * nsys, hipMemcpyHostToDevice, st),
+                       "upload state")))
+        return e;
+    for (int l = 0; l < sb.nlat; ++l) {
+        size_t n = (size_t)sb.nrhs[l] * sb.ctx[l]->Vh * 192;
+        if ((e = hip_check(c0, hipMemsetAsync(XH.p[l], 0, n, st), "memset x"))) return e;
+        if ((e = hip_check(c0, hipMemcpyAsync(RH.p[l], BH.p[l], n, hipMemcpyDeviceToDevice, st), "copy b")))
+            return e;
+    }
+    blas(lo64, OP_HI_TO_LO, {&R, &RH, &R0, &P, &XL}, 1, 3, nullptr);  // r = r0 = p = lo(b), xl = 0
+    hact.assign(nsys, 1);
+    hmask.assign(nsys, 0);
+    if ((e = hip_check(c0, hipMemcpyAsync(active, hact.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
+                       "upload active")))
+        return e;
+    auto cg_start = [&](const int *msk) {
+        // z = Dhat^+ r (|z|^2 -> slot 2); |r|^2 already in slot 5; p = z
+        dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, true, false);
+        dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, msk, true, false);
+        scal(SC_CG_INIT, msk);
+        blas(lo64, OP_ZERO, {&P}, 0, 0, msk);
+        blas(lo64, OP_CG_P, {&P, &S}, 0, 0, msk);  // SC_CG_INIT sets beta = 0: p = z
+    };
+    if (solver == FL_SOLVER_CGNR) {
+        cg_start(nullptr);
+    } else {
+        scal(SC_INIT, nullptr);
+    }
+
+    res.assign(nsys, SysResult());
+    std::vector<int> done(nsys, 0), restarts(nsys, 0);
+    const int chunk = trunc ? 2 : 8;
+    active_count.assign(sb.nlat, 0);
+    int ndone = 0;
+    auto sys_lat = [&](int k) {
+        int l = 0;
+        for (int q = 1; q < B.nlat; ++q)
+            if (k >= B.lat[q].sys0) l = q;
+        return l;
+    };
+    size_t prof_mark = c0->prof[FL_PROF_DSLASH].ev.size();
+    auto account_prof = [&]() {
+        ProfSlot &ps = c0->prof[FL_PROF_DSLASH];
+        if (!ps.on) return;
+        size_t nnew = ps.ev.size() - prof_mark;
+        prof_mark = ps.ev.size();
+        if (!nnew) return;
+        // algorithmic bytes of one hopping launch: every link once per
+        // lattice, plus each input spinor read once and each output written
+        // once for the systems still iterating (counted at the end of the
+        // chunk: a lower bound)
+        double bytes = 0;
+        for (int l = 0; l < B.nlat; ++l) {
+            int lb = fmt == LINK_F64_R18 ? 144 : (fmt == LINK_F32_R18 ? 72 : (fmt == LINK_F32_R12 ? 48 : 24));
+            bytes += 8.0 * lb * B.lat[l].Vh + 2.0 * lo_bytes_per_site_rhs() * B.lat[l].Vh * active_count[l];
+        }
+        ps.bytes += bytes * nnew;
+    };
+
+    while (ndone < nsys) {
+        // check the state every chunk of iterations
+        bool any_active = false;
+        for (int k = 0; k < nsys; ++k) any_active |= (hact[k] != 0);
+        if (any_active)
+            for (int it = 0; it < chunk; ++it) {
+                if (solver == FL_SOLVER_CGNR)
+                    cg_iteration();
+                else
+                    bicg_iteration();
+            }
+        if ((e = hip_check(c0, hipMemcpyAsync(hst.data(), dst, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, st),
+                           "download state")))
+            return e;
+        if ((e = hip_check(c0, hipMemcpyAsync(hact.data(), active, sizeof(int) * nsys, hipMemcpyDeviceToHost, st),
+                           "download active")))
+            return e;
+        if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
+        for (int l = 0; l < sb.nlat; ++l) active_count[l] = 0;
+        for (int k = 0; k < nsys; ++k)
+            if (hact[k]) active_count[sys_lat(k)]++;
+        account_prof();
+
+        bool any_upd = false, any_restart = false;
+        std::vector<int> final_upd(nsys, 0), restart(nsys, 0);
+        for (int k = 0; k < nsys; ++k) {
+            hmask[k] = 0;
+            if (done[k]) continue;
+            const int f = hst[k].flags;
+            if (trunc) {
+                if (f & (ST_CONV_ITER | ST_MAXIT | ST_BREAK)) {
+                    done[k] = 1;
+                    ++ndone;
+                    res[k].converged = (f & ST_CONV_ITER) ? 1 : 0;
+                    res[k].flags = f;
+                }
+                continue;
+            }
+            if (f & ST_BREAK) {
+                if (restarts[k] < 4 && hst[k].iter < hst[k].max_iter) {
+                    restart[k] = 1;
+                    any_restart = true;
+                    restarts[k]++;
+                } else {
+                    final_upd[k] = 1;
+                    hmask[k] = 1;
+                    any_upd = true;
+                }
+            } else if (f & (ST_CONV_ITER | ST_WANT_UPD | ST_MAXIT)) {
+                hmask[k] = 1;
+                any_upd = true;
+                if (f & ST_MAXIT) final_upd[k] = 1;
+            }
+        }
+        if (any_restart) {
+            // breakdown: fresh recurrence from the current FP64 iterate
+            std::vector<int> m(nsys, 0);
+            for (int k = 0; k < nsys; ++k) m[k] = restart[k];
+            if ((e = hip_check(c0, hipMemcpyAsync(mask, m.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
+                               "upload mask")))
+                return e;
+            replace_residual(mask, 1);
+            if ((e = hip_check(c0, hipMemcpyAsync(hst.data(), dst, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, st),
+                               "download state")))
+                return e;
+            if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
+            for (int k = 0; k < nsys; ++k)
+                if (restart[k]) {
+                    hst[k].flags = 0;
+                    res[k].updates++;
+                }
+            if ((e = hip_check(c0, hipMemcpyAsync(dst, hst.data(), sizeof(SysState) * nsys, hipMemcpyHostToDevice, st),
+                               "upload state")))
+                return e;
+            if (solver == FL_SOLVER_CGNR)
+                cg_start(mask);
+            else
+                scal(SC_INIT, mask);
+            if ((e = hip_check(c0, hipMemcpyAsync(hact.data(), active, sizeof(int) * nsys, hipMemcpyDeviceToHost, st),
+                               "download active")))
+                return e;
+            if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
+        }
+        if (any_upd) {
+            if ((e = hip_check(c0, hipMemcpyAsync(mask, hmask.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
+                               "upload mask")))
+                return e;
+            replace_residual(mask, solver == FL_SOLVER_CGNR ? 1 : 0);
+            scal(SC_RESET, mask);
+            if ((e = hip_check(c0, hipMemcpyAsync(hst.data(), dst, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, st),
+                               "download state")))
+                return e;
+            if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
+            for (int k = 0; k < nsys; ++k) {
+                if (!hmask[k]) continue;
+                res[k].updates++;
+                const SysState &s = hst[k];
+                bool ok = s.tr2 <= s.tstop2;
+                if (ok || final_upd[k] || s.iter >= s.max_iter) {
+                    done[k] = 1;
+                    ++ndone;
+                    hact[k] = 0;
+                    res[k].converged = ok ? 1 : 0;
+                    res[k].flags = s.flags | (final_upd[k] ? ST_MAXIT : 0);
+                } else {
+                    hact[k] = 1;
+                }
+            }
+            if (solver == FL_SOLVER_CGNR) {
+                // CGNR restarts from the replaced residual: z = Dhat^+ r, p = z
+                std::vector<int> m(nsys, 0);
+                for (int k = 0; k < nsys; ++k) m[k] = hmask[k] && hact[k];
+                if ((e = hip_check(c0, hipMemcpyAsync(mask, m.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
+                                   "upload mask")))
+                    return e;
+                cg_start(mask);
+            }
+            if ((e = hip_check(c0, hipMemcpyAsync(active, hact.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
+                               "upload active")))
+                return e;
+        }
+        // a system with nothing left to do must not spin the loop
+        if (!any_upd && !any_restart) {
+            bool progressing = false;
+            for (int k = 0; k < nsys; ++k) progressing |= (!done[k] && hact[k]);
+            if (!progressing)
+                for (int k = 0; k < nsys; ++k)
+                    if (!done[k]) {
+                        done[k] = 1;
+                        ++ndone;
+                        res[k].flags = hst[k].flags;
+                    }
+        }
+    }
+    if (trunc) {
+        // the LP solution is the low-precision iterate
+        blas(lo64, OP_ACC_HI, {&XH, &XL}, 0, 0, nullptr);
+    }
+    fl_status out = FL_OK;
+    for (int k = 0; k < nsys; ++k) {
+        const SysState &s = hst[k];
+        res[k].iters = s.iter;
+        double bn = sb.bnorm[k] > 0 ? sb.bnorm[k] : 1.0;
+        res[k].true_resid = trunc ? std::sqrt(s.rr) / bn : std::sqrt(s.tr2) / bn;
+        if (!res[k].converged) out = (res[k].flags & ST_BREAK) ? FL_ERR_BREAKDOWN : FL_ERR_NOCONV;
+    }
+    if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
+    return out;
+}
+
+}  // namespace
+
+fl_status solve_schur_batch(SolveBatch &sb, const fl_solver_params &p, std::vector<SysResult> &res)
+{
+    Solver s(sb, p);
+    return s.run(res);
+}
