@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark: stochastic disconnected loops on a 16^3 x 32 lattice (one GPU).
+
+Workload (the paper's lattice shape, Sec. II; synthetic links stand in for
+its SESAM ensemble): U = exp(i eps H) with eps = 0.6, kappa = 0.1596 (about
+400 FP64 BiCGStab iterations to 1e-12), antiperiodic time; Z4 noise with
+spin-colour-time dilution, 12 x 32 = 384 diluted sources per noise vector.
+One step = one noise vector: noise generation, even-odd preparation, 384
+batched Schur solves to |Dx-b|/|b| <= 1e-12 (FP32 iteration with FP32
+12-real links, FP64 reliable updates), odd-site reconstruction and the
+contraction of Eq. (loop stochastic) for Gamma = 1, g5, g1..g4.
+
+Prints one JSON line:  value = diluted solves per second (whole job).
+roofline: the hopping kernel of the iteration (events around every launch
+on the library's stream), algorithmic bytes = 8 links + input + output per
+site and right-hand side.  cpu_baseline: the FP64 oracle solving one of the
+same diluted sources on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Wilson solves/sec + dslash HBM GB/s at 16^3x32; loop rel. err vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def diluted_source(xi, t, spin, col, dims):
+    """eta = P_d xi for the time/spin/colour component (t, spin, col)."""
+    import numpy as np
+    Vs = dims[0] * dims[1] * dims[2]
+    eta = np.zeros_like(xi)
+    eta[Vs * t:Vs * (t + 1), spin, col] = xi[Vs * t:Vs * (t + 1), spin, col]
+    return eta
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", choices=["f32", "bf16"], default="f32")
+    ap.add_argument("--batch", type=int, default=384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-rhs", type=int, default=4, help="single-RHS FP64 GPU solves for the reference rate")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards over "
+              "independent sources and needs no multi-GPU run here", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1108_2473_amd as fl
+    import synth_inputs as S
+
+    W = S.WORKLOADS["stoch_16x16x16x32"]
+    dims, eps, kappa, bc = W["dims"], W["eps"], W["kappa"], W["bc_t"]
+    gam = fl.GAMMAS_PAPER
+    log(f"[bench] links {dims} eps={eps} kappa={kappa}")
+    U = S.random_links(dims, eps, W["link_seed"])
+    lat = fl.Lattice(dims, bc, device=0)
+    lat.set_gauge(U)
+    lat.set_kappa(kappa)
+    prec = fl.PREC_F32 if args.prec == "f32" else fl.PREC_BF16
+    lp = fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, batch=args.batch)
+    nt = dims[3]
+    solves_per_step = 12 * nt
+
+    def step(r):
+        q = fl.NoiseParams(noise=fl.NOISE_Z4, seed=W["noise_seed"], r0=r, n_lp=1, n_hp=0,
+                           dilution=fl.DIL_TIME | fl.DIL_SPIN | fl.DIL_COLOUR, t_begin=0, t_end=nt)
+        return lat.loops_stochastic(q, gam, lp=lp)
+
+    for k in range(args.warmup):
+        t0 = time.perf_counter()
+        step(1000 + k)
+        log(f"[bench] warmup step {k}: {time.perf_counter() - t0:.2f}s")
+    lat.profile_enable(fl.PROF_DSLASH, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+        log(f"[bench] step {k} done at {time.perf_counter() - t0:.2f}s")
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    prof = lat.profile_read(fl.PROF_DSLASH)
+    lat.profile_enable(fl.PROF_DSLASH, False)
+    value = solves_per_step * args.steps / T
+    achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
+    avg_us = prof["ms"] * 1e3 / max(1, prof["launches"])
+    log(f"[bench] {value:.1f} solves/s; hopping kernel {prof['launches']} launches, avg {avg_us:.1f} us, "
+        f"{achieved:.0f} GB/s")
+
+    # accuracy and the plain FP64 single-RHS reference on sources of the same workload
+    import oracle as O
+    xi = O.noise(O.NOISE_Z4, W["noise_seed"], 0, dims)
+    srcs = [diluted_source(xi, t, s, 0, dims) for (t, s) in [(0, 0), (5, 1), (17, 2), (31, 3)]]
+    b = np.stack(srcs[:max(1, args.fp64_rhs)])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(b.shape[0]):
+        x64, info64 = lat.solve(b[k:k + 1], fl.SolverParams(tol=1e-12, inner_prec=fl.PREC_F64, gauge_reals=18))
+    torch.cuda.synchronize()
+    fp64_rate = b.shape[0] / (time.perf_counter() - t1)
+    x_mp, info_mp = lat.solve(b[:1], fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12))
+    log(f"[bench] FP64 single-RHS GPU: {fp64_rate:.2f} solves/s ({info64[0]['iters']} iterations); "
+        f"mixed: {info_mp[0]['iters']} iterations, {info_mp[0]['updates']} FP64 updates")
+
+    cpu = None
+    loop_err = None
+    if not args.no_cpu_baseline:
+        t2 = time.perf_counter()
+        x_or, it_or, res_or, fails = O.solve(U, b[:1], dims, bc, kappa, tol=1e-12, max_iter=1200)
+        t_or = time.perf_counter() - t2
+        cpu = {"value": 1.0 / t_or, "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"one spin-colour-time diluted Z4 source of the same 16^3x32 workload solved "
+                         f"by the FP64 oracle (even-odd BiCGStab, {int(it_or[0])} iterations, "
+                         f"|Dx-b|/|b| = {res_or[0]:.1e}) in {t_or:.1f} s"}
+        # loop error vs FP64: this source's contribution eta^+ Gamma phi on its timeslice
+        Vs = dims[0] * dims[1] * dims[2]
+        e = b[0, :Vs]
+        errs = []
+        l1 = None
+        for g in gam:
+            G = O.gamma(g)
+            lg = np.einsum("sac,ab,sbc->s", e.conj(), G, x_mp[0, :Vs])
+            lo = np.einsum("sac,ab,sbc->s", e.conj(), G, x_or[0, :Vs])
+            if l1 is None:
+                l1 = np.abs(lo).max()
+            errs.append(np.abs(lg - lo).max() / l1)
+        loop_err = max(errs)
+        log(f"[bench] oracle {t_or:.1f}s ({O.num_threads()} threads); loop rel err vs FP64 {loop_err:.2e}")
+
+    bytes_per_launch = prof["bytes"] / max(1, prof["launches"])
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(T * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded SU(3) links exp(i*0.6*H), Z4 noise; stands in for the 16^3x32 SESAM ensemble)",
+        "config": {
+            "workload": "stochastic loops, 16^3x32 lattice, eps=0.6, kappa=0.1596, Z4 noise, "
+                        "spin-colour-time dilution, 384 diluted solves per step (one noise vector), "
+                        "tol 1e-12 on the full operator, Gamma = 1, g5, g1..g4",
+            "lattice": list(dims),
+            "solves_per_step": solves_per_step,
+            "inner": f"{args.prec} links (12 reals), fp32 vectors, fp64 reliable updates",
+            "batch": args.batch,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "kernel": "hopping term H_oe (FP32 12-real links), iteration launches",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_launch_us": round(avg_us, 2),
+            "launches": prof["launches"],
+            "algorithmic_bytes_per_launch": round(bytes_per_launch),
+        },
+        "cpu_baseline": cpu,
+        "fp64_single_rhs_gpu_solves_per_s": round(fp64_rate, 3),
+        "speedup_vs_fp64_single_rhs": round(value / fp64_rate, 3),
+        "loop_rel_err_vs_fp64": loop_err,
+        "iterations": {"fp64_single": info64[0]["iters"], "mixed": info_mp[0]["iters"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
