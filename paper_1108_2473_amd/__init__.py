@@ -17,7 +17,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libfloop.so")
+# FLOOP_LIB selects another build of the same library (e.g. a debug build)
+LIB_PATH = os.environ.get("FLOOP_LIB") or os.path.join(_HERE, "_lib", "libfloop.so")
 
 FL_HOST, FL_DEVICE = 0, 1
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
@@ -132,12 +133,14 @@ def lib():
                                 ctypes.POINTER(_SolverParams), vp, dp, i]
     L.fl_profile_enable.argtypes = [vp, i, i]
     L.fl_profile_read.argtypes = [vp, i, dp, ctypes.POINTER(ll), dp]
-    L.fl_bench_dslash.argtypes = [vp, i, i, i, i, i, dp, dp]
+    L.fl_bench_dslash.argtypes = [vp, i, i, i, i, i, i, i, dp, dp]
+    L.fl_set_tile.argtypes = [vp, i, i, i, i]
+    L.fl_autotune.argtypes = [vp, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i), dp]
     L.fl_solver_params_default.argtypes = [ctypes.POINTER(_SolverParams)]
     for name in ("fl_create", "fl_destroy", "fl_set_stream", "fl_set_gauge", "fl_set_kappa", "fl_apply_D",
                  "fl_solve", "fl_loops_exact", "fl_loops_exact_sites", "fl_loops_stochastic",
                  "fl_loops_stochastic_multi", "fl_loops_grad", "fl_profile_enable", "fl_profile_read",
-                 "fl_bench_dslash"):
+                 "fl_bench_dslash", "fl_set_tile", "fl_autotune"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -341,11 +344,20 @@ class Lattice:
         self._check(lib().fl_profile_read(self._h, kernel, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
         return dict(ms=ms.value, launches=n.value, bytes=b.value)
 
-    def bench_dslash(self, prec=PREC_F32, gauge_reals=12, nrhs=1, nrep=100, nsets=8):
+    def bench_dslash(self, prec=PREC_F32, gauge_reals=12, nrhs=1, nrep=100, nsets=8, rt=0, group=0):
         ms, b = ctypes.c_double(), ctypes.c_double()
-        self._check(lib().fl_bench_dslash(self._h, prec, gauge_reals, nrhs, nrep, nsets, ctypes.byref(ms),
-                                          ctypes.byref(b)))
-        return dict(ms=ms.value, bytes=b.value)
+        self._check(lib().fl_bench_dslash(self._h, prec, gauge_reals, nrhs, nrep, nsets, rt, group,
+                                          ctypes.byref(ms), ctypes.byref(b)))
+        return dict(ms=ms.value, bytes=b.value, gbs=b.value / ms.value / 1e6 if ms.value > 0 else 0.0)
+
+    def set_tile(self, prec=PREC_F32, gauge_reals=12, rt=0, group=0):
+        self._check(lib().fl_set_tile(self._h, prec, gauge_reals, rt, group))
+
+    def autotune(self, prec=PREC_F32, gauge_reals=12, nrhs=1):
+        rt, g, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self._check(lib().fl_autotune(self._h, prec, gauge_reals, nrhs, ctypes.byref(rt), ctypes.byref(g),
+                                      ctypes.byref(ms)))
+        return dict(rt=rt.value, group=g.value, ms=ms.value)
 
 
 def loops_stochastic_multi(lattices, noises, gammas, lp: SolverParams = None, hp: SolverParams = None,

@@ -111,12 +111,13 @@ fl_status check_params(fl_ctx *c, const fl_solver_params *p)
 void hop64(fl_ctx *c, int nrhs, int par, const void *in, void *out, const void *x, double ca, double cb, bool dag,
            int epi = -1)
 {
-    int RT = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
+    int RT, G;
+    tile_shape(c, LINK_F64_R18, nrhs, &RT, &G);
     fl_ctx *cs[1] = {c};
     int nr[1] = {nrhs};
     DslashArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.B = batch_geom(cs, nr, 1, RT);
+    a.B = batch_geom(cs, nr, 1, RT, G);
     a.par = par;
     a.nsys = nrhs;
     a.in[0] = in;
@@ -133,10 +134,11 @@ void hop64(fl_ctx *c, int nrhs, int par, const void *in, void *out, const void *
 // a fixed order
 fl_status norms64(fl_ctx *c, int nrhs, const void *fe, const void *fo, std::vector<double> &out)
 {
-    int RT = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
+    int RT, G;
+    tile_shape(c, LINK_F64_R18, nrhs, &RT, &G);
     fl_ctx *cs[1] = {c};
     int nr[1] = {nrhs};
-    BatchGeom B = batch_geom(cs, nr, 1, RT);
+    BatchGeom B = batch_geom(cs, nr, 1, RT, G);
     size_t np = 6 * (size_t)nrhs * B.nsb_max;
     double *part = (double *)ws_get(c, WS_MISC, np * sizeof(double));
     if (!part) return set_err(c, FL_ERR_NOMEM, "device allocation failed (norms)");
@@ -241,12 +243,13 @@ LatGeom lat_geom(const fl_ctx *c, int nrhs)
     return g;
 }
 
-BatchGeom batch_geom(fl_ctx *const *ctx, const int *nrhs, int nlat, int RT)
+BatchGeom batch_geom(fl_ctx *const *ctx, const int *nrhs, int nlat, int RT, int G)
 {
     BatchGeom B;
     std::memset(&B, 0, sizeof(B));
     B.nlat = nlat;
     B.RT = RT;
+    B.G = G > 0 ? G : 1;
     int tiles = 0, sys = 0;
     for (int l = 0; l < nlat; ++l) {
         LatGeom g = lat_geom(ctx[l], nrhs[l]);
@@ -260,6 +263,20 @@ BatchGeom batch_geom(fl_ctx *const *ctx, const int *nrhs, int nlat, int RT)
     }
     B.ntiles = tiles;
     return B;
+}
+
+void tile_shape(const fl_ctx *c, int fmt, int nrhs, int *RT, int *G)
+{
+    const int maxrt = fmt == LINK_F64_R18 ? 8 : 16;
+    // built-in choice (measured on the 16^3x32 hopping kernel): 8 right-hand
+    // sides per workgroup (4 in FP64), swept right-hand-side-block by block
+    // so that the stencil's neighbours are still in L2 when reused
+    int rt = c->tune_rt[fmt] > 0 ? c->tune_rt[fmt] : (fmt == LINK_F64_R18 ? 4 : 8);
+    // no more waves per workgroup than right-hand sides (next power of two)
+    int cap = 1;
+    while (cap < nrhs && cap < maxrt) cap *= 2;
+    *RT = std::max(1, std::min(std::min(rt, maxrt), cap));
+    *G = c->tune_g[fmt] > 0 ? c->tune_g[fmt] : 1;
 }
 
 void *links(fl_ctx *c, LinkFormat fmt)
@@ -347,7 +364,9 @@ fl_status fl_create(fl_ctx **out, int device, const int dims[4], int bc_t)
         if (dims[mu] < 2 || dims[mu] % 2) return set_err(nullptr, FL_ERR_ARG, "lattice extents must be even and >= 2");
     if (bc_t != 1 && bc_t != -1) return set_err(nullptr, FL_ERR_ARG, "bc_t must be +1 or -1");
     long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
-    if (V / 2 > (1LL << 30)) return set_err(nullptr, FL_ERR_ARG, "lattice too large");
+    // kernels address a whole link array (8 x 144 bytes per site pair in
+    // FP64) through 32-bit buffer offsets
+    if ((V / 2) * 8 * 144 >= (1LL << 31)) return set_err(nullptr, FL_ERR_ARG, "lattice too large (V <= 3.7M sites)");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         (void)hipGetLastError();
@@ -534,7 +553,9 @@ fl_status fl_solve(fl_ctx *c, const double *b, double *x, int nrhs, const fl_sol
             int nr[1] = {n};
             BlasArgs a;
             std::memset(&a, 0, sizeof(a));
-            a.B = batch_geom(cs, nr, 1, n >= 4 ? 4 : (n >= 2 ? 2 : 1));
+            int RT, G;
+            tile_shape(c, LINK_F64_R18, n, &RT, &G);
+            a.B = batch_geom(cs, nr, 1, RT, G);
             a.op = OP_SUB_HI;
             a.nsys = n;
             a.f[0][0] = he;
@@ -1068,24 +1089,24 @@ fl_status fl_profile_read(fl_ctx *c, int kernel, double *ms, long long *launches
     return FL_OK;
 }
 
-fl_status fl_bench_dslash(fl_ctx *c, int prec, int gauge_reals, int nrhs, int nrep, int nsets, double *ms_per_launch,
-                          double *bytes_per_launch)
+static fl_status fmt_of(fl_ctx *c, int prec, int gauge_reals, LinkFormat *fmt)
 {
-    if (!valid_ctx(c)) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
-    if (nrhs < 1 || nrep < 1 || nsets < 1 || nsets > 64) return set_err(c, FL_ERR_ARG, "bad benchmark sizes");
-    fl_status e;
-    if ((e = check_ready(c))) return e;
-    LinkFormat fmt;
-    if (prec == FL_PREC_F64)
-        fmt = LINK_F64_R18;
+    if (prec == FL_PREC_F64 && gauge_reals == 18)
+        *fmt = LINK_F64_R18;
     else if (prec == FL_PREC_F32)
-        fmt = gauge_reals == 18 ? LINK_F32_R18 : LINK_F32_R12;
+        *fmt = gauge_reals == 18 ? LINK_F32_R18 : LINK_F32_R12;
     else if (prec == FL_PREC_BF16 && gauge_reals == 12)
-        fmt = LINK_BF16_R12;
+        *fmt = LINK_BF16_R12;
     else
         return set_err(c, FL_ERR_ARG, "unsupported precision / link storage");
-    if ((fmt == LINK_F32_R12 || fmt == LINK_BF16_R12) && !c->su3)
+    if ((*fmt == LINK_F32_R12 || *fmt == LINK_BF16_R12) && !c->su3)
         return set_err(c, FL_ERR_ARG, "12-real links need SU(3) links");
+    return FL_OK;
+}
+
+static fl_status bench_impl(fl_ctx *c, LinkFormat fmt, int nrhs, int nrep, int nsets, int rt, int group,
+                            double *ms_per_launch, double *bytes_per_launch)
+{
     hipSetDevice(c->device);
     hipStream_t st = c->stream;
     const size_t sb = (fmt == LINK_F64_R18) ? 192 : 96;
@@ -1093,26 +1114,34 @@ fl_status fl_bench_dslash(fl_ctx *c, int prec, int gauge_reals, int nrhs, int nr
     const size_t fbytes = (size_t)nrhs * c->Vh * sb, gbytes = lb * 4 * (size_t)c->V;
     void *src = links(c, fmt);
     if (!src) return set_err(c, FL_ERR_NOMEM, "device allocation failed (links)");
-    std::vector<void *> ins(nsets), outs(nsets), gs(nsets);
+    std::vector<void *> ins(nsets, nullptr), outs(nsets, nullptr), gs(nsets, nullptr);
+    auto release = [&]() {
+        for (int q = 0; q < nsets; ++q) {
+            if (ins[q]) hipFree(ins[q]);
+            if (outs[q]) hipFree(outs[q]);
+            if (gs[q]) hipFree(gs[q]);
+        }
+    };
     for (int k = 0; k < nsets; ++k) {
         if (hipMalloc(&ins[k], fbytes) != hipSuccess || hipMalloc(&outs[k], fbytes) != hipSuccess ||
             hipMalloc(&gs[k], gbytes) != hipSuccess) {
             (void)hipGetLastError();
-            for (int q = 0; q <= k; ++q) {
-                if (ins[q]) hipFree(ins[q]);
-                if (outs[q]) hipFree(outs[q]);
-                if (gs[q]) hipFree(gs[q]);
-            }
+            release();
             return set_err(c, FL_ERR_NOMEM, "device allocation failed (benchmark buffers)");
         }
         hipMemsetAsync(ins[k], 0x3c, fbytes, st);
         hipMemcpyAsync(gs[k], src, gbytes, hipMemcpyDeviceToDevice, st);
     }
+    int RT, G;
+    tile_shape(c, fmt, nrhs, &RT, &G);
+    const int maxrt = fmt == LINK_F64_R18 ? 8 : 16;
+    if (rt > 0) RT = std::min(rt, maxrt);
+    if (group > 0) G = group;
     fl_ctx *cs[1] = {c};
     int nr[1] = {nrhs};
     DslashArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.B = batch_geom(cs, nr, 1, nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1));
+    a.B = batch_geom(cs, nr, 1, RT, G);
     a.par = 0;
     a.nsys = nrhs;
     a.cb[0] = 1.0;
@@ -1129,19 +1158,82 @@ fl_status fl_bench_dslash(fl_ctx *c, int prec, int gauge_reals, int nrhs, int nr
     hipEventRecord(t0, st);
     for (int r = 0; r < nrep; ++r) launch(r % nsets);
     hipEventRecord(t1, st);
-    e = hip_check(c, hipEventSynchronize(t1), "benchmark");
+    fl_status e = hip_check(c, hipEventSynchronize(t1), "benchmark");
     float ms = 0;
     hipEventElapsedTime(&ms, t0, t1);
     hipEventDestroy(t0);
     hipEventDestroy(t1);
-    for (int k = 0; k < nsets; ++k) {
-        hipFree(ins[k]);
-        hipFree(outs[k]);
-        hipFree(gs[k]);
-    }
+    release();
     if (e) return e;
     if (ms_per_launch) *ms_per_launch = ms / nrep;
     if (bytes_per_launch) *bytes_per_launch = (double)(8 * lb * c->Vh) + 2.0 * (double)fbytes;
+    return FL_OK;
+}
+
+fl_status fl_bench_dslash(fl_ctx *c, int prec, int gauge_reals, int nrhs, int nrep, int nsets, int rt, int group,
+                          double *ms_per_launch, double *bytes_per_launch)
+{
+    if (!valid_ctx(c)) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
+    if (nrhs < 1 || nrep < 1 || nsets < 1 || nsets > 64 || rt < 0 || rt > 16 || group < 0)
+        return set_err(c, FL_ERR_ARG, "bad benchmark sizes");
+    fl_status e;
+    if ((e = check_ready(c))) return e;
+    LinkFormat fmt;
+    if ((e = fmt_of(c, prec, gauge_reals, &fmt))) return e;
+    return bench_impl(c, fmt, nrhs, nrep, nsets, rt, group, ms_per_launch, bytes_per_launch);
+}
+
+fl_status fl_set_tile(fl_ctx *c, int prec, int gauge_reals, int rt, int group)
+{
+    if (!valid_ctx(c)) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
+    if (rt < 0 || rt > 16 || (rt & (rt - 1)) || group < 0)
+        return set_err(c, FL_ERR_ARG, "rt must be 0 or a power of two <= 16, group >= 0");
+    LinkFormat fmt;
+    if (prec == FL_PREC_F64 && gauge_reals == 18)
+        fmt = LINK_F64_R18;
+    else if (prec == FL_PREC_F32)
+        fmt = gauge_reals == 18 ? LINK_F32_R18 : LINK_F32_R12;
+    else if (prec == FL_PREC_BF16 && gauge_reals == 12)
+        fmt = LINK_BF16_R12;
+    else
+        return set_err(c, FL_ERR_ARG, "unsupported precision / link storage");
+    c->tune_rt[fmt] = rt;
+    c->tune_g[fmt] = group;
+    return FL_OK;
+}
+
+fl_status fl_autotune(fl_ctx *c, int prec, int gauge_reals, int nrhs, int *rt_out, int *group_out, double *ms_out)
+{
+    if (!valid_ctx(c)) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
+    if (nrhs < 1) return set_err(c, FL_ERR_ARG, "nrhs must be >= 1");
+    fl_status e;
+    if ((e = check_ready(c))) return e;
+    LinkFormat fmt;
+    if ((e = fmt_of(c, prec, gauge_reals, &fmt))) return e;
+    const int maxrt = fmt == LINK_F64_R18 ? 8 : 16;
+    double best = 1e300;
+    int brt = 0, bg = 0;
+    for (int rt = 1; rt <= maxrt; rt *= 2) {
+        if (rt > 1 && rt / 2 >= nrhs) break;
+        int nrb = (nrhs + rt - 1) / rt;
+        for (int g = 1;; g *= 2) {
+            int gg = std::min(g, nrb);
+            double ms = 0;
+            // two buffer sets larger than the on-chip caches, a few repetitions
+            if ((e = bench_impl(c, fmt, nrhs, 6, 2, rt, gg, &ms, nullptr))) return e;
+            if (ms < best) {
+                best = ms;
+                brt = rt;
+                bg = gg;
+            }
+            if (gg == nrb) break;
+        }
+    }
+    c->tune_rt[fmt] = brt;
+    c->tune_g[fmt] = bg;
+    if (rt_out) *rt_out = brt;
+    if (group_out) *group_out = bg;
+    if (ms_out) *ms_out = best;
     return FL_OK;
 }
 

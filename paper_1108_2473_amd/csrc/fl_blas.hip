@@ -18,18 +18,15 @@
 
 namespace {
 
+// per-wave buffer view of right-hand side `rhs` of a field stored as
+// SpinorFmt<R> (one resource per field, built in scalar registers)
 template <typename R>
-struct Fld {
-    typedef typename SpinorFmt<R>::V V;
-    __device__ static __forceinline__ const V *cptr(const void *base, const LatGeom &g, int rhs)
-    {
-        return (const V *)base + (size_t)rhs * SpinorFmt<R>::NC * g.Vh;
-    }
-    __device__ static __forceinline__ V *ptr(void *base, const LatGeom &g, int rhs)
-    {
-        return (V *)base + (size_t)rhs * SpinorFmt<R>::NC * g.Vh;
-    }
-};
+__device__ __forceinline__ Buf fbuf(const void *base, const LatGeom &g, int rhs)
+{
+    const size_t fs = (size_t)SpinorFmt<R>::NC * g.Vh;
+    const unsigned bytes = (unsigned)(fs * sizeof(typename SpinorFmt<R>::V));
+    return make_buf((const typename SpinorFmt<R>::V *)base + rhs * fs, bytes);
+}
 
 template <typename R>
 __device__ __forceinline__ cx<R> cpx_of(const double *v)
@@ -38,13 +35,14 @@ __device__ __forceinline__ cx<R> cpx_of(const double *v)
 }
 
 template <typename R, int OP>
-__global__ __launch_bounds__(256) void k_blas(BlasArgs a)
+__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_blas(BlasArgs a)
 {
     TileInfo T = tile_info(a.B);
     if (!T.valid_rhs) return;
     if (a.mask && !a.mask[T.sys]) return;
     const LatGeom &g = a.B.lat[T.lat];
-    const int l = T.lat, rhs = T.rhs, i = T.site, Vh = g.Vh;
+    const int l = T.lat, i = T.site, Vh = g.Vh;
+    const int rhs = __builtin_amdgcn_readfirstlane(T.rhs);
     typedef SpinorFmt<R> F;
     typedef SpinorFmt<double> F64;
     R q0 = 0, q1 = 0, q2 = 0;
@@ -53,59 +51,59 @@ __global__ __launch_bounds__(256) void k_blas(BlasArgs a)
             const SysState &st = a.st[T.sys];
             cx<R> al = cpx_of<R>(st.alpha);
             cx<R> r[12], v[12];
-            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, r);
-            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, v);
+            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, r);
+            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, v);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) r[k] = r[k] - al * v[k];
-            F::store(Fld<R>::ptr(a.f[2][l], g, rhs), Vh, i, r);
+            for (int k = 0; k < 12; ++k) r[k] = cmsub(r[k], al, v[k]);
+            F::store(fbuf<R>(a.f[2][l], g, rhs), Vh, i, r);
         } else if (OP == OP_BICG_XR) {
             const SysState &st = a.st[T.sys];
             cx<R> al = cpx_of<R>(st.alpha), om = cpx_of<R>(st.omega);
             cx<R> x[12], p[12], s[12], t[12], r0[12];
-            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, x);
-            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, p);
-            F::load(Fld<R>::cptr(a.f[2][l], g, rhs), Vh, i, s);
-            F::load(Fld<R>::cptr(a.f[3][l], g, rhs), Vh, i, t);
-            F::load(Fld<R>::cptr(a.f[5][l], g, rhs), Vh, i, r0);
+            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, x);
+            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, p);
+            F::load(fbuf<R>(a.f[2][l], g, rhs), Vh, i, s);
+            F::load(fbuf<R>(a.f[3][l], g, rhs), Vh, i, t);
+            F::load(fbuf<R>(a.f[5][l], g, rhs), Vh, i, r0);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                x[k] = x[k] + al * p[k] + om * s[k];
-                s[k] = s[k] - om * t[k];  // new r
+                x[k] = cmad(cmad(x[k], al, p[k]), om, s[k]);
+                s[k] = cmsub(s[k], om, t[k]);  // new r
                 cx<R> d = cjmul(r0[k], s[k]);
                 q0 += d.re;
                 q1 += d.im;
                 q2 += s[k].re * s[k].re + s[k].im * s[k].im;
             }
-            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, x);
-            F::store(Fld<R>::ptr(a.f[4][l], g, rhs), Vh, i, s);
+            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, x);
+            F::store(fbuf<R>(a.f[4][l], g, rhs), Vh, i, s);
         } else if (OP == OP_BICG_P) {
             const SysState &st = a.st[T.sys];
             cx<R> be = cpx_of<R>(st.beta), om = cpx_of<R>(st.omega);
             cx<R> p[12], r[12], v[12];
-            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, p);
-            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, r);
-            F::load(Fld<R>::cptr(a.f[2][l], g, rhs), Vh, i, v);
+            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, p);
+            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, r);
+            F::load(fbuf<R>(a.f[2][l], g, rhs), Vh, i, v);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) p[k] = r[k] + be * (p[k] - om * v[k]);
-            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, p);
+            for (int k = 0; k < 12; ++k) p[k] = cmad(r[k], be, cmsub(p[k], om, v[k]));
+            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, p);
         } else if (OP == OP_HI_TO_LO) {
             cx<double> h[12];
             cx<R> lo[12], r0[12];
-            F64::load(Fld<double>::cptr(a.f[1][l], g, rhs), Vh, i, h);
+            F64::load(fbuf<double>(a.f[1][l], g, rhs), Vh, i, h);
 #pragma unroll
             for (int k = 0; k < 12; ++k) lo[k] = cx<R>{(R)h[k].re, (R)h[k].im};
-            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, lo);
+            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, lo);
             if (a.flag) {
-                F::store(Fld<R>::ptr(a.f[2][l], g, rhs), Vh, i, lo);
-                F::store(Fld<R>::ptr(a.f[3][l], g, rhs), Vh, i, lo);
+                F::store(fbuf<R>(a.f[2][l], g, rhs), Vh, i, lo);
+                F::store(fbuf<R>(a.f[3][l], g, rhs), Vh, i, lo);
                 cx<R> z[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) z[k] = cx<R>{(R)0, (R)0};
-                F::store(Fld<R>::ptr(a.f[4][l], g, rhs), Vh, i, z);
+                F::store(fbuf<R>(a.f[4][l], g, rhs), Vh, i, z);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) r0[k] = lo[k];
             } else {
-                F::load(Fld<R>::cptr(a.f[2][l], g, rhs), Vh, i, r0);
+                F::load(fbuf<R>(a.f[2][l], g, rhs), Vh, i, r0);
             }
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
@@ -117,56 +115,56 @@ __global__ __launch_bounds__(256) void k_blas(BlasArgs a)
         } else if (OP == OP_ACC_HI) {
             cx<double> h[12];
             cx<R> lo[12];
-            F64::load(Fld<double>::cptr(a.f[0][l], g, rhs), Vh, i, h);
-            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, lo);
+            F64::load(fbuf<double>(a.f[0][l], g, rhs), Vh, i, h);
+            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, lo);
 #pragma unroll
             for (int k = 0; k < 12; ++k) h[k] = h[k] + cx<double>{(double)lo[k].re, (double)lo[k].im};
-            F64::store(Fld<double>::ptr(a.f[0][l], g, rhs), Vh, i, h);
+            F64::store(fbuf<double>(a.f[0][l], g, rhs), Vh, i, h);
             if (a.flag) {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) lo[k] = cx<R>{(R)0, (R)0};
-                F::store(Fld<R>::ptr(a.f[1][l], g, rhs), Vh, i, lo);
+                F::store(fbuf<R>(a.f[1][l], g, rhs), Vh, i, lo);
             }
         } else if (OP == OP_SUB_HI) {
             cx<double> u[12], w[12];
-            F64::load(Fld<double>::cptr(a.f[1][l], g, rhs), Vh, i, u);
-            F64::load(Fld<double>::cptr(a.f[2][l], g, rhs), Vh, i, w);
+            F64::load(fbuf<double>(a.f[1][l], g, rhs), Vh, i, u);
+            F64::load(fbuf<double>(a.f[2][l], g, rhs), Vh, i, w);
 #pragma unroll
             for (int k = 0; k < 12; ++k) u[k] = u[k] - w[k];
-            F64::store(Fld<double>::ptr(a.f[0][l], g, rhs), Vh, i, u);
+            F64::store(fbuf<double>(a.f[0][l], g, rhs), Vh, i, u);
         } else if (OP == OP_NORM) {
             cx<R> f[12];
-            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, f);
+            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, f);
 #pragma unroll
             for (int k = 0; k < 12; ++k) q2 += f[k].re * f[k].re + f[k].im * f[k].im;
         } else if (OP == OP_ZERO) {
             cx<R> z[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) z[k] = cx<R>{(R)0, (R)0};
-            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, z);
+            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, z);
         } else if (OP == OP_CG_XR) {
             const R al = (R)a.st[T.sys].alpha[0];
             cx<R> x[12], r[12], p[12], q[12];
-            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, x);
-            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, r);
-            F::load(Fld<R>::cptr(a.f[2][l], g, rhs), Vh, i, p);
-            F::load(Fld<R>::cptr(a.f[3][l], g, rhs), Vh, i, q);
+            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, x);
+            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, r);
+            F::load(fbuf<R>(a.f[2][l], g, rhs), Vh, i, p);
+            F::load(fbuf<R>(a.f[3][l], g, rhs), Vh, i, q);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                x[k] = x[k] + al * p[k];
-                r[k] = r[k] - al * q[k];
+                x[k] = cx<R>{fma(al, p[k].re, x[k].re), fma(al, p[k].im, x[k].im)};
+                r[k] = cx<R>{fma(-al, q[k].re, r[k].re), fma(-al, q[k].im, r[k].im)};
                 q2 += r[k].re * r[k].re + r[k].im * r[k].im;
             }
-            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, x);
-            F::store(Fld<R>::ptr(a.f[1][l], g, rhs), Vh, i, r);
+            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, x);
+            F::store(fbuf<R>(a.f[1][l], g, rhs), Vh, i, r);
         } else if (OP == OP_CG_P) {
             const R be = (R)a.st[T.sys].beta[0];
             cx<R> p[12], z[12];
-            F::load(Fld<R>::cptr(a.f[0][l], g, rhs), Vh, i, p);
-            F::load(Fld<R>::cptr(a.f[1][l], g, rhs), Vh, i, z);
+            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, p);
+            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, z);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) p[k] = z[k] + be * p[k];
-            F::store(Fld<R>::ptr(a.f[0][l], g, rhs), Vh, i, p);
+            for (int k = 0; k < 12; ++k) p[k] = cx<R>{fma(be, p[k].re, z[k].re), fma(be, p[k].im, z[k].im)};
+            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, p);
         }
     }
     if (OP == OP_BICG_XR || OP == OP_HI_TO_LO || OP == OP_NORM || OP == OP_CG_XR) {

@@ -56,6 +56,95 @@ __device__ __forceinline__ cx<R> cjmul(cx<R> a, cx<R> b)
     return cx<R>{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 
+// acc + a * b as four fused multiply-adds (the compiler cannot reassociate
+// acc + (a*b) into this form by itself)
+template <typename R>
+__device__ __forceinline__ cx<R> cmad(cx<R> acc, cx<R> a, cx<R> b)
+{
+    R re = fma(a.re, b.re, acc.re);
+    R im = fma(a.re, b.im, acc.im);
+    re = fma(-a.im, b.im, re);
+    im = fma(a.im, b.re, im);
+    return cx<R>{re, im};
+}
+
+// acc + conj(a) * b
+template <typename R>
+__device__ __forceinline__ cx<R> cjmad(cx<R> acc, cx<R> a, cx<R> b)
+{
+    R re = fma(a.re, b.re, acc.re);
+    R im = fma(a.re, b.im, acc.im);
+    re = fma(a.im, b.im, re);
+    im = fma(-a.im, b.re, im);
+    return cx<R>{re, im};
+}
+
+// acc - a * b
+template <typename R>
+__device__ __forceinline__ cx<R> cmsub(cx<R> acc, cx<R> a, cx<R> b)
+{
+    R re = fma(-a.re, b.re, acc.re);
+    R im = fma(-a.re, b.im, acc.im);
+    re = fma(a.im, b.im, re);
+    im = fma(-a.im, b.re, im);
+    return cx<R>{re, im};
+}
+
+// ---------------------------------------------------------------------------
+// buffer views: a raw buffer resource per field and wavefront (scalar
+// registers), so that each load is one buffer instruction with a 32-bit
+// per-lane offset and a scalar component offset, and no 64-bit address
+// arithmetic per lane
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ __forceinline__ Buf make_buf(const void *base, unsigned bytes)
+{
+    Buf b;
+    b.r = __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, 0x00020000);
+    return b;
+}
+
+__device__ __forceinline__ v4f buf_ld16(const Buf &b, int voff, int soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b128(b.r, voff, soff, 0);
+}
+
+__device__ __forceinline__ v2f buf_ld8(const Buf &b, int voff, int soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b64(b.r, voff, soff, 0);
+}
+
+__device__ __forceinline__ void buf_st16(const Buf &b, v4f v, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(v, b.r, voff, soff, 0);
+}
+
+__device__ __forceinline__ double2 v4f_to_d2(v4f v)
+{
+    union {
+        v4f f;
+        double2 d;
+    } u;
+    u.f = v;
+    return u.d;
+}
+
+__device__ __forceinline__ v4f d2_to_v4f(double2 d)
+{
+    union {
+        v4f f;
+        double2 d;
+    } u;
+    u.d = d;
+    return u.f;
+}
+
 // ---------------------------------------------------------------------------
 // spinor storage: 24 reals (spin-major, colour, re/im) per site
 // ---------------------------------------------------------------------------
@@ -79,6 +168,20 @@ struct SpinorFmt<double> {
 #pragma unroll
         for (int c = 0; c < 12; ++c) f[(size_t)c * Vh + i] = make_double2(s[c].re, s[c].im);
     }
+    // buffer views of one right-hand side's field (component stride Vh*16 bytes)
+    __device__ static __forceinline__ void load(const Buf &b, int Vh, int i, cx<double> s[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            double2 v = v4f_to_d2(buf_ld16(b, i * 16, c * Vh * 16));
+            s[c] = cx<double>{v.x, v.y};
+        }
+    }
+    __device__ static __forceinline__ void store(const Buf &b, int Vh, int i, const cx<double> s[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) buf_st16(b, d2_to_v4f(make_double2(s[c].re, s[c].im)), i * 16, c * Vh * 16);
+    }
 };
 
 template <>
@@ -99,6 +202,23 @@ struct SpinorFmt<float> {
 #pragma unroll
         for (int c = 0; c < 6; ++c)
             f[(size_t)c * Vh + i] = make_float4(s[2 * c].re, s[2 * c].im, s[2 * c + 1].re, s[2 * c + 1].im);
+    }
+    __device__ static __forceinline__ void load(const Buf &b, int Vh, int i, cx<float> s[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            v4f v = buf_ld16(b, i * 16, c * Vh * 16);
+            s[2 * c] = cx<float>{v.x, v.y};
+            s[2 * c + 1] = cx<float>{v.z, v.w};
+        }
+    }
+    __device__ static __forceinline__ void store(const Buf &b, int Vh, int i, const cx<float> s[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            v4f v = {s[2 * c].re, s[2 * c].im, s[2 * c + 1].re, s[2 * c + 1].im};
+            buf_st16(b, v, i * 16, c * Vh * 16);
+        }
     }
 };
 
@@ -136,9 +256,9 @@ template <typename R>
 __device__ __forceinline__ void rebuild_row2(cx<R> U[3][3])
 {
     // row2 = conj(row0 x row1)
-    U[2][0] = cj(U[0][1] * U[1][2] - U[0][2] * U[1][1]);
-    U[2][1] = cj(U[0][2] * U[1][0] - U[0][0] * U[1][2]);
-    U[2][2] = cj(U[0][0] * U[1][1] - U[0][1] * U[1][0]);
+    U[2][0] = cj(cmsub(U[0][1] * U[1][2], U[0][2], U[1][1]));
+    U[2][1] = cj(cmsub(U[0][2] * U[1][0], U[0][0], U[1][2]));
+    U[2][2] = cj(cmsub(U[0][0] * U[1][1], U[0][1], U[1][0]));
 }
 
 struct LinkF64R18 {
@@ -147,6 +267,15 @@ struct LinkF64R18 {
     static constexpr int NC = 9;
     static constexpr int REALS = 18;
     static constexpr int BYTES = 144;
+    static constexpr int ESZ = 16;
+    __device__ static __forceinline__ void load(const Buf &g, int Vh, int soff0, int i, cx<double> U[3][3])
+    {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            double2 v = v4f_to_d2(buf_ld16(g, i * 16, soff0 + c * Vh * 16));
+            U[c / 3][c % 3] = cx<double>{v.x, v.y};
+        }
+    }
     __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<double> U[3][3])
     {
 #pragma unroll
@@ -163,6 +292,15 @@ struct LinkF32R18 {
     static constexpr int NC = 9;
     static constexpr int REALS = 18;
     static constexpr int BYTES = 72;
+    static constexpr int ESZ = 8;
+    __device__ static __forceinline__ void load(const Buf &g, int Vh, int soff0, int i, cx<float> U[3][3])
+    {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            v2f v = buf_ld8(g, i * 8, soff0 + c * Vh * 8);
+            U[c / 3][c % 3] = cx<float>{v.x, v.y};
+        }
+    }
     __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<float> U[3][3])
     {
 #pragma unroll
@@ -179,6 +317,18 @@ struct LinkF32R12 {
     static constexpr int NC = 3;
     static constexpr int REALS = 12;
     static constexpr int BYTES = 48;
+    static constexpr int ESZ = 16;
+    __device__ static __forceinline__ void load(const Buf &g, int Vh, int soff0, int i, cx<float> U[3][3])
+    {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v4f v = buf_ld16(g, i * 16, soff0 + c * Vh * 16);
+            int e = 2 * c;
+            U[e / 3][e % 3] = cx<float>{v.x, v.y};
+            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{v.z, v.w};
+        }
+        rebuild_row2(U);
+    }
     __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<float> U[3][3])
     {
 #pragma unroll
@@ -198,6 +348,24 @@ struct LinkBF16R12 {
     static constexpr int NC = 3;
     static constexpr int REALS = 12;
     static constexpr int BYTES = 24;
+    static constexpr int ESZ = 8;
+    __device__ static __forceinline__ void load(const Buf &g, int Vh, int soff0, int i, cx<float> U[3][3])
+    {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v2f f = buf_ld8(g, i * 8, soff0 + c * Vh * 8);
+            union {
+                v2f f;
+                uint2 u;
+            } cv;
+            cv.f = f;
+            uint2 v = cv.u;
+            int e = 2 * c;
+            U[e / 3][e % 3] = cx<float>{bf16_to_f32(v.x & 0xffffu), bf16_to_f32(v.x >> 16)};
+            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{bf16_to_f32(v.y & 0xffffu), bf16_to_f32(v.y >> 16)};
+        }
+        rebuild_row2(U);
+    }
     __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<float> U[3][3])
     {
 #pragma unroll
@@ -230,6 +398,7 @@ struct BatchGeom {
     int nlat;
     int ntiles;
     int RT;       // right-hand sides (wavefronts) per workgroup
+    int G;        // right-hand-side blocks that sweep the site blocks together
     int nsb_max;  // stride of per-system partial arrays
     LatGeom lat[FL_MAXLAT];
 };
@@ -264,9 +433,17 @@ __device__ __forceinline__ TileInfo tile_info(const BatchGeom &B)
     for (int k = 1; k < FL_MAXLAT; ++k)
         if (k < B.nlat && tile >= B.lat[k].tile0) l = k;
     const LatGeom &g = B.lat[l];
+    // tiles of a lattice: groups of G right-hand-side blocks; within a group
+    // the site blocks are swept in order with the group's blocks innermost
     int local = tile - g.tile0;
-    int sb = local / g.nrb;
-    int rb = local - sb * g.nrb;
+    int G = B.G < g.nrb ? B.G : g.nrb;
+    int span = g.nsb * G;
+    int grp = local / span;
+    int rem = local - grp * span;
+    int Gg = g.nrb - grp * G;
+    if (Gg > G) Gg = G;
+    int sb = rem / Gg;
+    int rb = grp * G + (rem - sb * Gg);
     int wave = threadIdx.x / FL_WAVE;
     int lane = threadIdx.x % FL_WAVE;
     TileInfo t;

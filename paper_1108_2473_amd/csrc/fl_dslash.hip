@@ -26,28 +26,39 @@
 namespace {
 
 template <typename R, class LK, bool DAG, int EPI>
-__global__ __launch_bounds__(256) void k_dslash(DslashArgs a)
+__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_dslash(DslashArgs a)
 {
     typedef typename SpinorFmt<R>::V SV;
     TileInfo T = tile_info(a.B);
     if (!T.valid_rhs) return;
     if (a.mask && !a.mask[T.sys]) return;  // wave-uniform: one wave = one right-hand side
     const LatGeom &g = a.B.lat[T.lat];
+    const int rhs = __builtin_amdgcn_readfirstlane(T.rhs);
     const size_t fs = (size_t)SpinorFmt<R>::NC * g.Vh;
+    const unsigned fbytes = (unsigned)(fs * sizeof(SV));
     R q0 = 0, q1 = 0, q2 = 0;
     if (T.valid_site) {
         Coord c = cb_coords(g, a.par, T.site);
-        const SV *in = (const SV *)a.in[T.lat] + T.rhs * fs;
+        BufSrc<R, LK> src;
+        src.in = make_buf((const SV *)a.in[T.lat] + rhs * fs, fbytes);
+        src.gauge = make_buf(a.gauge[T.lat], (unsigned)(8u * LK::NC * LK::ESZ * (unsigned)g.Vh));
+        src.Vh = g.Vh;
         cx<R> acc[12];
-        hop_site<DAG, R, LK>(g, a.par, T.site, c, in, (const typename LK::V *)a.gauge[T.lat], acc);
+        hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
         const R cb = (R)a.cb[T.lat];
         cx<R> out[12];
         if (EPI & EPI_XPAY) {
             cx<R> xv[12];
-            SpinorFmt<R>::load((const SV *)a.x[T.lat] + T.rhs * fs, g.Vh, T.site, xv);
+            SpinorFmt<R>::load(make_buf((const SV *)a.x[T.lat] + rhs * fs, fbytes), g.Vh, T.site, xv);
             const R ca = (R)a.ca[T.lat];
+            if (ca == (R)1) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) out[k] = ca * xv[k] + cb * acc[k];
+                for (int k = 0; k < 12; ++k)
+                    out[k] = cx<R>{fma(cb, acc[k].re, xv[k].re), fma(cb, acc[k].im, xv[k].im)};
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) out[k] = ca * xv[k] + cb * acc[k];
+            }
             if (EPI & EPI_DOTX_NORM) {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) {
@@ -61,10 +72,10 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a)
 #pragma unroll
             for (int k = 0; k < 12; ++k) out[k] = cb * acc[k];
         }
-        SpinorFmt<R>::store((SV *)a.out[T.lat] + T.rhs * fs, g.Vh, T.site, out);
+        SpinorFmt<R>::store(make_buf((SV *)a.out[T.lat] + rhs * fs, fbytes), g.Vh, T.site, out);
         if (EPI & EPI_DOTY) {
             cx<R> yv[12];
-            SpinorFmt<R>::load((const SV *)a.y[T.lat] + T.rhs * fs, g.Vh, T.site, yv);
+            SpinorFmt<R>::load(make_buf((const SV *)a.y[T.lat] + rhs * fs, fbytes), g.Vh, T.site, yv);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 cx<R> d = cjmul(yv[k], out[k]);

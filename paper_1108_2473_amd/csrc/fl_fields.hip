@@ -235,7 +235,8 @@ __global__ void k_exact_contract(ExactContractArgs a)
                 c.t = ls.t;
                 c.rest = ls.y + g.L[1] * (ls.z + g.L[2] * ls.t);
                 cx<double> h[12], b[12];
-                hop_site<false, double, LinkF64R18>(g, 1, ls.cb, c, a.xe + j * fs, a.gauge, h);
+                PtrSrc<double, LinkF64R18> src{a.xe + j * fs, a.gauge, g.Vh};
+                hop_site<false, double>(g, 1, ls.cb, c, src, h);
                 SpinorFmt<double>::load(a.bo + j * fs, g.Vh, ls.cb, b);
                 for (int q = 0; q < 12; ++q) psi[q] = b[q] + a.kappa * h[q];
             }

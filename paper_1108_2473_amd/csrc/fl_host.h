@@ -224,6 +224,8 @@ struct fl_ctx {
     std::string err;
     std::vector<DevBuf> pool;  // named workspace buffers
     ProfSlot prof[FL_PROF_NKERNELS];
+    int tune_rt[4] = {0, 0, 0, 0};  // per LinkFormat; 0: heuristic
+    int tune_g[4] = {0, 0, 0, 0};
 };
 
 fl_status set_err(fl_ctx *c, fl_status st, const std::string &msg);
@@ -232,7 +234,11 @@ fl_status hip_check(fl_ctx *c, hipError_t e, const char *what);
 void *ws_get(fl_ctx *c, int slot, size_t bytes);
 void *links(fl_ctx *c, LinkFormat fmt);  // device links in that format (built on first use)
 LatGeom lat_geom(const fl_ctx *c, int nrhs);
-BatchGeom batch_geom(fl_ctx *const *ctx, const int *nrhs, int nlat, int RT);
+BatchGeom batch_geom(fl_ctx *const *ctx, const int *nrhs, int nlat, int RT, int G = 1 << 20);
+// workgroup shape of the batched kernels for link format fmt and nrhs
+// right-hand sides: RT waves (right-hand sides) per workgroup and G
+// right-hand-side blocks per site sweep (the autotuner's choice if any)
+void tile_shape(const fl_ctx *c, int fmt, int nrhs, int *RT, int *G);
 // kernel profiling hooks (events on the context stream)
 void prof_begin(fl_ctx *c, int kernel);
 void prof_end(fl_ctx *c, int kernel, double bytes);

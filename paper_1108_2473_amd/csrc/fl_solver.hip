@@ -183,8 +183,9 @@ fl_status Solver::run(std::vector<SysResult> &res)
                 return set_err(c0, FL_ERR_ARG, "12-real link storage needs SU(3) links; use gauge_reals = 18");
     int minr = 1 << 30;
     for (int l = 0; l < sb.nlat; ++l) minr = std::min(minr, std::max(1, sb.nrhs[l]));
-    const int RT = minr >= 4 ? 4 : (minr >= 2 ? 2 : 1);
-    B = batch_geom(sb.ctx, sb.nrhs, sb.nlat, RT);
+    int RT, G;
+    tile_shape(c0, fmt, minr, &RT, &G);
+    B = batch_geom(sb.ctx, sb.nrhs, sb.nlat, RT, G);
     nsys = 0;
     for (int l = 0; l < sb.nlat; ++l) nsys += sb.nrhs[l];
     if (nsys == 0) return FL_OK;

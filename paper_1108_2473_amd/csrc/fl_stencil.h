@@ -61,8 +61,8 @@ __device__ __forceinline__ void link_mul(const cx<R> U[3][3], const cx<R> h[6], 
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             cx<R> acc = U[a][0] * h[3 * sp];
-            acc = acc + U[a][1] * h[3 * sp + 1];
-            acc = acc + U[a][2] * h[3 * sp + 2];
+            acc = cmad(acc, U[a][1], h[3 * sp + 1]);
+            acc = cmad(acc, U[a][2], h[3 * sp + 2]);
             w[3 * sp + a] = sgn * acc;
         }
 }
@@ -76,63 +76,82 @@ __device__ __forceinline__ void link_adj_mul(const cx<R> U[3][3], const cx<R> h[
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             cx<R> acc = cjmul(U[0][a], h[3 * sp]);
-            acc = acc + cjmul(U[1][a], h[3 * sp + 1]);
-            acc = acc + cjmul(U[2][a], h[3 * sp + 2]);
+            acc = cjmad(acc, U[1][a], h[3 * sp + 1]);
+            acc = cjmad(acc, U[2][a], h[3 * sp + 2]);
             w[3 * sp + a] = sgn * acc;
         }
 }
 
-template <int MU, bool DAG, typename R, class LK>
-__device__ __forceinline__ void hop_dir(int Vh, int p, int i, int nf, int nb, R sf, R sb,
-                                        const typename SpinorFmt<R>::V *__restrict__ in,
-                                        const typename LK::V *__restrict__ gauge, cx<R> acc[12])
+// Where the stencil reads its input spinor field and links from: plain
+// pointers (any lane layout) or per-wave buffer views (scalar resources).
+template <typename R, class LK>
+struct PtrSrc {
+    const typename SpinorFmt<R>::V *in;
+    const typename LK::V *gauge;
+    int Vh;
+    __device__ __forceinline__ void spinor(int i, cx<R> s[12]) const { SpinorFmt<R>::load(in, Vh, i, s); }
+    __device__ __forceinline__ void link(int mu, int par, int i, cx<R> U[3][3]) const
+    {
+        LK::load(gauge + (size_t)(mu * 2 + par) * LK::NC * Vh, Vh, i, U);
+    }
+};
+
+template <typename R, class LK>
+struct BufSrc {
+    Buf in, gauge;
+    int Vh;
+    __device__ __forceinline__ void spinor(int i, cx<R> s[12]) const { SpinorFmt<R>::load(in, Vh, i, s); }
+    __device__ __forceinline__ void link(int mu, int par, int i, cx<R> U[3][3]) const
+    {
+        LK::load(gauge, Vh, (mu * 2 + par) * LK::NC * Vh * LK::ESZ, i, U);
+    }
+};
+
+template <int MU, bool DAG, typename R, class SRC>
+__device__ __forceinline__ void hop_dir(int p, int i, int nf, int nb, R sf, R sb, const SRC &src, cx<R> acc[12])
 {
     constexpr int SF = DAG ? 1 : -1;
     constexpr int SB = DAG ? -1 : 1;
     cx<R> psi[12], h[6], w[6], U[3][3];
     // forward hop: U_mu(x) psi(x + mu), link stored with the output parity
-    SpinorFmt<R>::load(in, Vh, nf, psi);
+    src.spinor(nf, psi);
     project<MU, SF>(psi, h);
-    LK::load(gauge + (size_t)(MU * 2 + p) * LK::NC * Vh, Vh, i, U);
+    src.link(MU, p, i, U);
     link_mul(U, h, sf, w);
     accumulate<MU, SF>(acc, w);
     // backward hop: U_mu(x - mu)^+ psi(x - mu), link stored at the neighbour
-    SpinorFmt<R>::load(in, Vh, nb, psi);
+    src.spinor(nb, psi);
     project<MU, SB>(psi, h);
-    LK::load(gauge + (size_t)(MU * 2 + (1 - p)) * LK::NC * Vh, Vh, nb, U);
+    src.link(MU, 1 - p, nb, U);
     link_adj_mul(U, h, sb, w);
     accumulate<MU, SB>(acc, w);
 }
 
-template <bool DAG, typename R, class LK>
-__device__ __forceinline__ void hop_site(const LatGeom &g, int p, int i, const Coord &c,
-                                         const typename SpinorFmt<R>::V *__restrict__ in,
-                                         const typename LK::V *__restrict__ gauge, cx<R> acc[12])
+template <bool DAG, typename R, class SRC>
+__device__ __forceinline__ void hop_site(const LatGeom &g, int p, int i, const Coord &c, const SRC &src,
+                                         cx<R> acc[12])
 {
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = cx<R>{(R)0, (R)0};
-    const int Vh = g.Vh, Lh0 = g.Lh0, xh = c.x >> 1;
+    const int Lh0 = g.Lh0, xh = c.x >> 1;
     {   // x
         int xf = (c.x + 1 == g.L[0]) ? 0 : c.x + 1;
         int xb = (c.x == 0) ? g.L[0] - 1 : c.x - 1;
-        hop_dir<0, DAG, R, LK>(Vh, p, i, (xf >> 1) + Lh0 * c.rest, (xb >> 1) + Lh0 * c.rest,
-                               (R)1, (R)1, in, gauge, acc);
+        hop_dir<0, DAG, R>(p, i, (xf >> 1) + Lh0 * c.rest, (xb >> 1) + Lh0 * c.rest, (R)1, (R)1, src, acc);
     }
     const int Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
     {   // y
         int yf = (c.y + 1 == Ly) ? 0 : c.y + 1;
         int yb = (c.y == 0) ? Ly - 1 : c.y - 1;
         int zt = Ly * (c.z + Lz * c.t);
-        hop_dir<1, DAG, R, LK>(Vh, p, i, xh + Lh0 * (yf + zt), xh + Lh0 * (yb + zt), (R)1, (R)1,
-                               in, gauge, acc);
+        hop_dir<1, DAG, R>(p, i, xh + Lh0 * (yf + zt), xh + Lh0 * (yb + zt), (R)1, (R)1, src, acc);
     }
     {   // z
         int zf = (c.z + 1 == Lz) ? 0 : c.z + 1;
         int zb = (c.z == 0) ? Lz - 1 : c.z - 1;
         int base = xh + Lh0 * c.y;
         int s = Lh0 * Ly;
-        hop_dir<2, DAG, R, LK>(Vh, p, i, base + s * (zf + Lz * c.t), base + s * (zb + Lz * c.t),
-                               (R)1, (R)1, in, gauge, acc);
+        hop_dir<2, DAG, R>(p, i, base + s * (zf + Lz * c.t), base + s * (zb + Lz * c.t), (R)1, (R)1, src, acc);
     }
     {   // t, with the boundary factor on the hops that wrap
         int tf = c.t + 1, tb = c.t - 1;
@@ -141,7 +160,6 @@ __device__ __forceinline__ void hop_site(const LatGeom &g, int p, int i, const C
         if (tb < 0) { tb = Lt - 1; sb = (R)g.bc_t; }
         int base = xh + Lh0 * (c.y + Ly * c.z);
         int s = Lh0 * Ly * Lz;
-        hop_dir<3, DAG, R, LK>(Vh, p, i, base + s * tf, base + s * tb, sf, sb, in, gauge, acc);
+        hop_dir<3, DAG, R>(p, i, base + s * tf, base + s * tb, sf, sb, src, acc);
     }
 }
-
