@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--solver", choices=["cgnr", "bicgstab"], default="cgnr")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-rhs", type=int, default=4, help="single-RHS FP64 GPU solves for the reference rate")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="run only the warmup and timed steps (for kernel profiles of the timed region)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards over "
@@ -102,6 +104,11 @@ def main():
     log(f"[bench] {value:.1f} solves/s; hopping kernel {prof['launches']} launches, avg {avg_us:.1f} us, "
         f"{achieved:.0f} GB/s")
 
+    if args.timed_only:
+        print(json.dumps({"metric": METRIC, "value": round(value, 3), "unit": "solves/s", "steps": args.steps,
+                          "hopping_kernel": {"launches": prof["launches"], "avg_launch_us": round(avg_us, 2),
+                                             "achieved_GBs": round(achieved, 1)}}), flush=True)
+        return
     # accuracy and the plain FP64 single-RHS reference on sources of the same workload
     import oracle as O
     xi = O.noise(O.NOISE_Z4, W["noise_seed"], 0, dims)

@@ -233,23 +233,28 @@ fl_status fl_profile_read(fl_ctx *ctx, int kernel, double *ms, long long *launch
  * out_e = H_eo in_o for nrhs right-hand sides at precision `prec` and
  * gauge_reals, cycling through `nsets` independent buffer sets (links and
  * spinors, to defeat on-chip caches), timed with HIP events on the context
- * stream.  rt, group: workgroup shape (0: the context's current choice).
+ * stream.  rt, group, lds: workgroup shape and LDS staging (0, 0, -1: the
+ * context's current choice).
  * ms_per_launch and bytes_per_launch (algorithmic) are returned. */
 fl_status fl_bench_dslash(fl_ctx *ctx, int prec, int gauge_reals, int nrhs, int nrep,
-                          int nsets, int rt, int group, double *ms_per_launch,
+                          int nsets, int rt, int group, int lds, double *ms_per_launch,
                           double *bytes_per_launch);
 
 /* Workgroup shape of the batched kernels for one precision / link storage:
  * rt right-hand sides (wavefronts) per workgroup (power of two <= 16; FP64
- * uses at most 8) and `group` right-hand-side blocks that sweep the site
- * blocks together (0: all).  rt = 0 restores the built-in choice. */
-fl_status fl_set_tile(fl_ctx *ctx, int prec, int gauge_reals, int rt, int group);
+ * uses at most 8), `group` right-hand-side blocks that sweep the site
+ * blocks together (0: all), and lds, the LDS staging of the hopping kernel:
+ * 0 none, 1 each wavefront's x/y neighbour window, 2 windows plus the
+ * workgroup's links, -1 the built-in choice (2 when it fits).  rt = 0
+ * restores the built-in workgroup size. */
+fl_status fl_set_tile(fl_ctx *ctx, int prec, int gauge_reals, int rt, int group, int lds);
 
 /* Autotuner: time the hopping kernel for nrhs right-hand sides over the
- * workgroup shapes above and keep the fastest for this context (returned
- * in rt, group and its launch time in ms; any output pointer may be NULL). */
+ * workgroup shapes and LDS modes above and keep the fastest for this
+ * context (returned in rt, group, lds and its launch time in ms; any output
+ * pointer may be NULL). */
 fl_status fl_autotune(fl_ctx *ctx, int prec, int gauge_reals, int nrhs, int *rt, int *group,
-                      double *ms);
+                      int *lds, double *ms);
 
 /* Text of the last error of ctx (or of the last failed fl_create when ctx
  * is NULL). */

@@ -133,9 +133,9 @@ def lib():
                                 ctypes.POINTER(_SolverParams), vp, dp, i]
     L.fl_profile_enable.argtypes = [vp, i, i]
     L.fl_profile_read.argtypes = [vp, i, dp, ctypes.POINTER(ll), dp]
-    L.fl_bench_dslash.argtypes = [vp, i, i, i, i, i, i, i, dp, dp]
-    L.fl_set_tile.argtypes = [vp, i, i, i, i]
-    L.fl_autotune.argtypes = [vp, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i), dp]
+    L.fl_bench_dslash.argtypes = [vp, i, i, i, i, i, i, i, i, dp, dp]
+    L.fl_set_tile.argtypes = [vp, i, i, i, i, i]
+    L.fl_autotune.argtypes = [vp, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), dp]
     L.fl_solver_params_default.argtypes = [ctypes.POINTER(_SolverParams)]
     for name in ("fl_create", "fl_destroy", "fl_set_stream", "fl_set_gauge", "fl_set_kappa", "fl_apply_D",
                  "fl_solve", "fl_loops_exact", "fl_loops_exact_sites", "fl_loops_stochastic",
@@ -344,20 +344,20 @@ class Lattice:
         self._check(lib().fl_profile_read(self._h, kernel, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
         return dict(ms=ms.value, launches=n.value, bytes=b.value)
 
-    def bench_dslash(self, prec=PREC_F32, gauge_reals=12, nrhs=1, nrep=100, nsets=8, rt=0, group=0):
+    def bench_dslash(self, prec=PREC_F32, gauge_reals=12, nrhs=1, nrep=100, nsets=8, rt=0, group=0, lds=-1):
         ms, b = ctypes.c_double(), ctypes.c_double()
-        self._check(lib().fl_bench_dslash(self._h, prec, gauge_reals, nrhs, nrep, nsets, rt, group,
+        self._check(lib().fl_bench_dslash(self._h, prec, gauge_reals, nrhs, nrep, nsets, rt, group, lds,
                                           ctypes.byref(ms), ctypes.byref(b)))
         return dict(ms=ms.value, bytes=b.value, gbs=b.value / ms.value / 1e6 if ms.value > 0 else 0.0)
 
-    def set_tile(self, prec=PREC_F32, gauge_reals=12, rt=0, group=0):
-        self._check(lib().fl_set_tile(self._h, prec, gauge_reals, rt, group))
+    def set_tile(self, prec=PREC_F32, gauge_reals=12, rt=0, group=0, lds=-1):
+        self._check(lib().fl_set_tile(self._h, prec, gauge_reals, rt, group, lds))
 
     def autotune(self, prec=PREC_F32, gauge_reals=12, nrhs=1):
-        rt, g, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        rt, g, ld, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         self._check(lib().fl_autotune(self._h, prec, gauge_reals, nrhs, ctypes.byref(rt), ctypes.byref(g),
-                                      ctypes.byref(ms)))
-        return dict(rt=rt.value, group=g.value, ms=ms.value)
+                                      ctypes.byref(ld), ctypes.byref(ms)))
+        return dict(rt=rt.value, group=g.value, lds=ld.value, ms=ms.value)
 
 
 def loops_stochastic_multi(lattices, noises, gammas, lp: SolverParams = None, hp: SolverParams = None,

@@ -127,6 +127,7 @@ void hop64(fl_ctx *c, int nrhs, int par, const void *in, void *out, const void *
     a.ca[0] = ca;
     a.cb[0] = cb;
     if (epi < 0) epi = x ? EPI_XPAY : EPI_PLAIN;
+    dslash_config(c, LINK_F64_R18, a);
     launch_dslash(LINK_F64_R18, a, dag, epi, c->stream);
 }
 
@@ -271,12 +272,35 @@ void tile_shape(const fl_ctx *c, int fmt, int nrhs, int *RT, int *G)
     // built-in choice (measured on the 16^3x32 hopping kernel): 8 right-hand
     // sides per workgroup (4 in FP64), swept right-hand-side-block by block
     // so that the stencil's neighbours are still in L2 when reused
-    int rt = c->tune_rt[fmt] > 0 ? c->tune_rt[fmt] : (fmt == LINK_F64_R18 ? 4 : 8);
+    int rt = c->tune_rt[fmt] > 0 ? c->tune_rt[fmt] : (fmt == LINK_F64_R18 ? 2 : 8);
     // no more waves per workgroup than right-hand sides (next power of two)
     int cap = 1;
     while (cap < nrhs && cap < maxrt) cap *= 2;
     *RT = std::max(1, std::min(std::min(rt, maxrt), cap));
-    *G = c->tune_g[fmt] > 0 ? c->tune_g[fmt] : 1;
+    *G = c->tune_g[fmt] > 0 ? c->tune_g[fmt] : (fmt == LINK_F64_R18 ? 2 : 1);
+}
+
+void dslash_config(const fl_ctx *c, LinkFormat fmt, DslashArgs &a)
+{
+    // LDS window: the (z, t) planes that the 64 sites of a block lie in
+    int ws = 0;
+    for (int l = 0; l < a.B.nlat; ++l) {
+        const LatGeom &g = a.B.lat[l];
+        const int plane = g.Lh0 * g.L[1];
+        for (int i0 = 0; i0 < g.Vh; i0 += FL_WAVE) {
+            int lo = (i0 / plane) * plane;
+            int hi = std::min(g.Vh, (std::min(i0 + FL_WAVE, g.Vh) - 1) / plane * plane + plane);
+            ws = std::max(ws, hi - lo);
+            if (plane % FL_WAVE == 0 && i0 >= plane) break;  // every block alike
+        }
+    }
+    a.wsmax = ws;
+    int mode = c->tune_lds[fmt];
+    // built-in (measured at 16^3x32): FP32 windows and staged links, FP64
+    // windows only; a mode that does not fit the LDS falls back to the next
+    if (mode < 0) mode = fmt == LINK_F64_R18 ? 1 : 2;
+    while (mode > 0 && dslash_lds_bytes(fmt, a.B.RT, a.wsmax, mode) > c->max_lds) --mode;
+    a.lds = mode;
 }
 
 void *links(fl_ctx *c, LinkFormat fmt)
@@ -382,6 +406,9 @@ fl_status fl_create(fl_ctx **out, int device, const int dims[4], int bc_t)
     c->Vh = V / 2;
     c->Vs = (long long)dims[0] * dims[1] * dims[2];
     c->pool.resize(WS_NSLOTS);
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->max_lds = (size_t)lds;
     *out = c;
     return FL_OK;
 }
@@ -1104,7 +1131,7 @@ static fl_status fmt_of(fl_ctx *c, int prec, int gauge_reals, LinkFormat *fmt)
     return FL_OK;
 }
 
-static fl_status bench_impl(fl_ctx *c, LinkFormat fmt, int nrhs, int nrep, int nsets, int rt, int group,
+static fl_status bench_impl(fl_ctx *c, LinkFormat fmt, int nrhs, int nrep, int nsets, int rt, int group, int lds,
                             double *ms_per_launch, double *bytes_per_launch)
 {
     hipSetDevice(c->device);
@@ -1145,6 +1172,16 @@ static fl_status bench_impl(fl_ctx *c, LinkFormat fmt, int nrhs, int nrep, int n
     a.par = 0;
     a.nsys = nrhs;
     a.cb[0] = 1.0;
+    {
+        int saved = c->tune_lds[fmt];
+        if (lds >= 0) c->tune_lds[fmt] = lds;
+        dslash_config(c, fmt, a);
+        c->tune_lds[fmt] = saved;
+    }
+    if (lds > a.lds) {
+        release();
+        return set_err(c, FL_ERR_ARG, "LDS staging does not fit this workgroup shape");
+    }
     auto launch = [&](int k) {
         a.in[0] = ins[k];
         a.out[0] = outs[k];
@@ -1171,7 +1208,7 @@ static fl_status bench_impl(fl_ctx *c, LinkFormat fmt, int nrhs, int nrep, int n
 }
 
 fl_status fl_bench_dslash(fl_ctx *c, int prec, int gauge_reals, int nrhs, int nrep, int nsets, int rt, int group,
-                          double *ms_per_launch, double *bytes_per_launch)
+                          int lds, double *ms_per_launch, double *bytes_per_launch)
 {
     if (!valid_ctx(c)) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
     if (nrhs < 1 || nrep < 1 || nsets < 1 || nsets > 64 || rt < 0 || rt > 16 || group < 0)
@@ -1180,14 +1217,15 @@ fl_status fl_bench_dslash(fl_ctx *c, int prec, int gauge_reals, int nrhs, int nr
     if ((e = check_ready(c))) return e;
     LinkFormat fmt;
     if ((e = fmt_of(c, prec, gauge_reals, &fmt))) return e;
-    return bench_impl(c, fmt, nrhs, nrep, nsets, rt, group, ms_per_launch, bytes_per_launch);
+    if (lds < -1 || lds > 2) return set_err(c, FL_ERR_ARG, "lds must be -1, 0, 1 or 2");
+    return bench_impl(c, fmt, nrhs, nrep, nsets, rt, group, lds, ms_per_launch, bytes_per_launch);
 }
 
-fl_status fl_set_tile(fl_ctx *c, int prec, int gauge_reals, int rt, int group)
+fl_status fl_set_tile(fl_ctx *c, int prec, int gauge_reals, int rt, int group, int lds)
 {
     if (!valid_ctx(c)) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
-    if (rt < 0 || rt > 16 || (rt & (rt - 1)) || group < 0)
-        return set_err(c, FL_ERR_ARG, "rt must be 0 or a power of two <= 16, group >= 0");
+    if (rt < 0 || rt > 16 || (rt & (rt - 1)) || group < 0 || lds < -1 || lds > 2)
+        return set_err(c, FL_ERR_ARG, "rt must be 0 or a power of two <= 16, group >= 0, lds in -1..2");
     LinkFormat fmt;
     if (prec == FL_PREC_F64 && gauge_reals == 18)
         fmt = LINK_F64_R18;
@@ -1199,10 +1237,12 @@ fl_status fl_set_tile(fl_ctx *c, int prec, int gauge_reals, int rt, int group)
         return set_err(c, FL_ERR_ARG, "unsupported precision / link storage");
     c->tune_rt[fmt] = rt;
     c->tune_g[fmt] = group;
+    c->tune_lds[fmt] = lds;
     return FL_OK;
 }
 
-fl_status fl_autotune(fl_ctx *c, int prec, int gauge_reals, int nrhs, int *rt_out, int *group_out, double *ms_out)
+fl_status fl_autotune(fl_ctx *c, int prec, int gauge_reals, int nrhs, int *rt_out, int *group_out, int *lds_out,
+                      double *ms_out)
 {
     if (!valid_ctx(c)) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
     if (nrhs < 1) return set_err(c, FL_ERR_ARG, "nrhs must be >= 1");
@@ -1212,27 +1252,34 @@ fl_status fl_autotune(fl_ctx *c, int prec, int gauge_reals, int nrhs, int *rt_ou
     if ((e = fmt_of(c, prec, gauge_reals, &fmt))) return e;
     const int maxrt = fmt == LINK_F64_R18 ? 8 : 16;
     double best = 1e300;
-    int brt = 0, bg = 0;
-    for (int rt = 1; rt <= maxrt; rt *= 2) {
-        if (rt > 1 && rt / 2 >= nrhs) break;
-        int nrb = (nrhs + rt - 1) / rt;
-        for (int g = 1;; g *= 2) {
-            int gg = std::min(g, nrb);
-            double ms = 0;
-            // two buffer sets larger than the on-chip caches, a few repetitions
-            if ((e = bench_impl(c, fmt, nrhs, 6, 2, rt, gg, &ms, nullptr))) return e;
-            if (ms < best) {
-                best = ms;
-                brt = rt;
-                bg = gg;
+    int brt = 0, bg = 0, bl = 0;
+    for (int lds = 0; lds <= 2; ++lds)
+        for (int rt = 1; rt <= maxrt; rt *= 2) {
+            if (rt > 1 && rt / 2 >= nrhs) break;
+            int nrb = (nrhs + rt - 1) / rt;
+            for (int g = 1;; g *= 2) {
+                int gg = std::min(g, nrb);
+                double ms = 0;
+                // two buffer sets larger than the on-chip caches, a few repetitions
+                e = bench_impl(c, fmt, nrhs, 6, 2, rt, gg, lds, &ms, nullptr);
+                if (e == FL_ERR_ARG) break;  // staging does not fit this shape
+                if (e) return e;
+                if (ms < best) {
+                    best = ms;
+                    brt = rt;
+                    bg = gg;
+                    bl = lds;
+                }
+                if (gg == nrb) break;
             }
-            if (gg == nrb) break;
         }
-    }
+    c->err.clear();
     c->tune_rt[fmt] = brt;
     c->tune_g[fmt] = bg;
+    c->tune_lds[fmt] = bl;
     if (rt_out) *rt_out = brt;
     if (group_out) *group_out = bg;
+    if (lds_out) *lds_out = bl;
     if (ms_out) *ms_out = best;
     return FL_OK;
 }

@@ -261,6 +261,9 @@ __device__ __forceinline__ void rebuild_row2(cx<R> U[3][3])
     U[2][2] = cj(cmsub(U[0][0] * U[1][1], U[0][1], U[1][0]));
 }
 
+// Each format stores one link as NC vectors of type V; unpack() turns the
+// NC vectors into the 3x3 matrix (rebuilding row 2 for 12-real storage), so
+// global, buffer and LDS reads share the decoding.
 struct LinkF64R18 {
     typedef double R;
     typedef double2 V;
@@ -268,21 +271,14 @@ struct LinkF64R18 {
     static constexpr int REALS = 18;
     static constexpr int BYTES = 144;
     static constexpr int ESZ = 16;
-    __device__ static __forceinline__ void load(const Buf &g, int Vh, int soff0, int i, cx<double> U[3][3])
+    __device__ static __forceinline__ void unpack(const V v[NC], cx<double> U[3][3])
     {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            double2 v = v4f_to_d2(buf_ld16(g, i * 16, soff0 + c * Vh * 16));
-            U[c / 3][c % 3] = cx<double>{v.x, v.y};
-        }
+        for (int c = 0; c < 9; ++c) U[c / 3][c % 3] = cx<double>{v[c].x, v[c].y};
     }
-    __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<double> U[3][3])
+    __device__ static __forceinline__ V buf_get(const Buf &g, int voff, int soff)
     {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            V v = g[(size_t)c * Vh + i];
-            U[c / 3][c % 3] = cx<double>{v.x, v.y};
-        }
+        return v4f_to_d2(buf_ld16(g, voff, soff));
     }
 };
 
@@ -293,21 +289,15 @@ struct LinkF32R18 {
     static constexpr int REALS = 18;
     static constexpr int BYTES = 72;
     static constexpr int ESZ = 8;
-    __device__ static __forceinline__ void load(const Buf &g, int Vh, int soff0, int i, cx<float> U[3][3])
+    __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
     {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            v2f v = buf_ld8(g, i * 8, soff0 + c * Vh * 8);
-            U[c / 3][c % 3] = cx<float>{v.x, v.y};
-        }
+        for (int c = 0; c < 9; ++c) U[c / 3][c % 3] = cx<float>{v[c].x, v[c].y};
     }
-    __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<float> U[3][3])
+    __device__ static __forceinline__ V buf_get(const Buf &g, int voff, int soff)
     {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            V v = g[(size_t)c * Vh + i];
-            U[c / 3][c % 3] = cx<float>{v.x, v.y};
-        }
+        v2f f = buf_ld8(g, voff, soff);
+        return make_float2(f.x, f.y);
     }
 };
 
@@ -318,27 +308,20 @@ struct LinkF32R12 {
     static constexpr int REALS = 12;
     static constexpr int BYTES = 48;
     static constexpr int ESZ = 16;
-    __device__ static __forceinline__ void load(const Buf &g, int Vh, int soff0, int i, cx<float> U[3][3])
+    __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
     {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            v4f v = buf_ld16(g, i * 16, soff0 + c * Vh * 16);
-            int e = 2 * c;
-            U[e / 3][e % 3] = cx<float>{v.x, v.y};
-            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{v.z, v.w};
+            int e = 2 * c;  // complex entries 2c, 2c+1 of rows 0..1
+            U[e / 3][e % 3] = cx<float>{v[c].x, v[c].y};
+            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{v[c].z, v[c].w};
         }
         rebuild_row2(U);
     }
-    __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<float> U[3][3])
+    __device__ static __forceinline__ V buf_get(const Buf &g, int voff, int soff)
     {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            V v = g[(size_t)c * Vh + i];
-            int e = 2 * c;  // complex entries 2c, 2c+1 of rows 0..1
-            U[e / 3][e % 3] = cx<float>{v.x, v.y};
-            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{v.z, v.w};
-        }
-        rebuild_row2(U);
+        v4f f = buf_ld16(g, voff, soff);
+        return make_float4(f.x, f.y, f.z, f.w);
     }
 };
 
@@ -349,35 +332,47 @@ struct LinkBF16R12 {
     static constexpr int REALS = 12;
     static constexpr int BYTES = 24;
     static constexpr int ESZ = 8;
-    __device__ static __forceinline__ void load(const Buf &g, int Vh, int soff0, int i, cx<float> U[3][3])
+    __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
     {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            v2f f = buf_ld8(g, i * 8, soff0 + c * Vh * 8);
-            union {
-                v2f f;
-                uint2 u;
-            } cv;
-            cv.f = f;
-            uint2 v = cv.u;
             int e = 2 * c;
-            U[e / 3][e % 3] = cx<float>{bf16_to_f32(v.x & 0xffffu), bf16_to_f32(v.x >> 16)};
-            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{bf16_to_f32(v.y & 0xffffu), bf16_to_f32(v.y >> 16)};
+            U[e / 3][e % 3] = cx<float>{bf16_to_f32(v[c].x & 0xffffu), bf16_to_f32(v[c].x >> 16)};
+            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{bf16_to_f32(v[c].y & 0xffffu), bf16_to_f32(v[c].y >> 16)};
         }
         rebuild_row2(U);
     }
-    __device__ static __forceinline__ void load(const V *__restrict__ g, int Vh, int i, cx<float> U[3][3])
+    __device__ static __forceinline__ V buf_get(const Buf &g, int voff, int soff)
     {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            V v = g[(size_t)c * Vh + i];
-            int e = 2 * c;
-            U[e / 3][e % 3] = cx<float>{bf16_to_f32(v.x & 0xffffu), bf16_to_f32(v.x >> 16)};
-            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{bf16_to_f32(v.y & 0xffffu), bf16_to_f32(v.y >> 16)};
-        }
-        rebuild_row2(U);
+        v2f f = buf_ld8(g, voff, soff);
+        union {
+            v2f f;
+            uint2 u;
+        } cv;
+        cv.f = f;
+        return cv.u;
     }
 };
+
+// links of (direction mu, parity par) at checkerboard site i
+template <class LK>
+__device__ __forceinline__ void link_load(const typename LK::V *__restrict__ g, int Vh, int i,
+                                          cx<typename LK::R> U[3][3])
+{
+    typename LK::V v[LK::NC];
+#pragma unroll
+    for (int c = 0; c < LK::NC; ++c) v[c] = g[(size_t)c * Vh + i];
+    LK::unpack(v, U);
+}
+
+template <class LK>
+__device__ __forceinline__ void link_load(const Buf &g, int Vh, int soff0, int i, cx<typename LK::R> U[3][3])
+{
+    typename LK::V v[LK::NC];
+#pragma unroll
+    for (int c = 0; c < LK::NC; ++c) v[c] = LK::buf_get(g, i * LK::ESZ, soff0 + c * Vh * LK::ESZ);
+    LK::unpack(v, U);
+}
 
 // ---------------------------------------------------------------------------
 // geometry of a batch of lattices and the tile map

@@ -25,6 +25,72 @@
 
 namespace {
 
+template <typename R, int EPI>
+__device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T, const LatGeom &g, int rhs,
+                                         const cx<R> acc[12], R &q0, R &q1, R &q2)
+{
+    typedef typename SpinorFmt<R>::V SV;
+    const size_t fs = (size_t)SpinorFmt<R>::NC * g.Vh;
+    const unsigned fbytes = (unsigned)(fs * sizeof(SV));
+    const R cb = (R)a.cb[T.lat];
+    cx<R> out[12];
+    if (EPI & EPI_XPAY) {
+        cx<R> xv[12];
+        SpinorFmt<R>::load(make_buf((const SV *)a.x[T.lat] + rhs * fs, fbytes), g.Vh, T.site, xv);
+        const R ca = (R)a.ca[T.lat];
+        if (ca == (R)1) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) out[k] = cx<R>{fma(cb, acc[k].re, xv[k].re), fma(cb, acc[k].im, xv[k].im)};
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) out[k] = ca * xv[k] + cb * acc[k];
+        }
+        if (EPI & EPI_DOTX_NORM) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                cx<R> d = cjmul(out[k], xv[k]);
+                q0 += d.re;
+                q1 += d.im;
+                q2 += out[k].re * out[k].re + out[k].im * out[k].im;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) out[k] = cb * acc[k];
+    }
+    SpinorFmt<R>::store(make_buf((SV *)a.out[T.lat] + rhs * fs, fbytes), g.Vh, T.site, out);
+    if (EPI & EPI_DOTY) {
+        cx<R> yv[12];
+        SpinorFmt<R>::load(make_buf((const SV *)a.y[T.lat] + rhs * fs, fbytes), g.Vh, T.site, yv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            cx<R> d = cjmul(yv[k], out[k]);
+            q0 += d.re;
+            q1 += d.im;
+        }
+    }
+    if (EPI & EPI_NORM) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) q2 += out[k].re * out[k].re + out[k].im * out[k].im;
+    }
+}
+
+template <int EPI, typename R>
+__device__ __forceinline__ void reduce_partials(const DslashArgs &a, const TileInfo &T, R q0, R q1, R q2)
+{
+    if (EPI & (EPI_DOTY | EPI_DOTX_NORM | EPI_NORM)) {
+        double s0 = wave_sum((double)q0), s1 = wave_sum((double)q1), s2 = wave_sum((double)q2);
+        if (threadIdx.x % FL_WAVE == 0) {
+            const int ns = a.nsys, nb = a.B.nsb_max;
+            if (EPI & (EPI_DOTY | EPI_DOTX_NORM)) {
+                a.partial[pidx(a.slot0, ns, T.sys, nb, T.sb)] = s0;
+                a.partial[pidx(a.slot0 + 1, ns, T.sys, nb, T.sb)] = s1;
+            }
+            if (EPI & (EPI_DOTX_NORM | EPI_NORM)) a.partial[pidx(a.slot0 + 2, ns, T.sys, nb, T.sb)] = s2;
+        }
+    }
+}
+
 template <typename R, class LK, bool DAG, int EPI>
 __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_dslash(DslashArgs a)
 {
@@ -45,60 +111,160 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_dslash(DslashAr
         src.Vh = g.Vh;
         cx<R> acc[12];
         hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
-        const R cb = (R)a.cb[T.lat];
-        cx<R> out[12];
-        if (EPI & EPI_XPAY) {
-            cx<R> xv[12];
-            SpinorFmt<R>::load(make_buf((const SV *)a.x[T.lat] + rhs * fs, fbytes), g.Vh, T.site, xv);
-            const R ca = (R)a.ca[T.lat];
-            if (ca == (R)1) {
+        epilogue<R, EPI>(a, T, g, rhs, acc, q0, q1, q2);
+    }
+    reduce_partials<EPI>(a, T, q0, q1, q2);
+}
+
+template <typename R, class LK, bool SLINK>
+struct LdsSrc {
+    typedef typename SpinorFmt<R>::V SV;
+    Buf in, gauge;
+    int Vh, wlo, wsz, wsmax, p, lane;
+    const SV *win;
+    const typename LK::V *lk;
+    template <int MU>
+    __device__ __forceinline__ void spinor(int i, cx<R> s[12]) const
+    {
+        if (MU < 2)
+            SpinorFmt<R>::load(win, wsmax, i - wlo, s);
+        else
+            SpinorFmt<R>::load(in, Vh, i, s);
+    }
+    __device__ __forceinline__ void link(int mu, int par, int i, cx<R> U[3][3]) const
+    {
+        if (SLINK) {
+            const int dslot = 2 * mu + (par == p ? 0 : 1);
+            typename LK::V v[LK::NC];
 #pragma unroll
-                for (int k = 0; k < 12; ++k)
-                    out[k] = cx<R>{fma(cb, acc[k].re, xv[k].re), fma(cb, acc[k].im, xv[k].im)};
-            } else {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) out[k] = ca * xv[k] + cb * acc[k];
-            }
-            if (EPI & EPI_DOTX_NORM) {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    cx<R> d = cjmul(out[k], xv[k]);
-                    q0 += d.re;
-                    q1 += d.im;
-                    q2 += out[k].re * out[k].re + out[k].im * out[k].im;
-                }
-            }
+            for (int c = 0; c < LK::NC; ++c) v[c] = lk[(dslot * LK::NC + c) * FL_WAVE + lane];
+            LK::unpack(v, U);
         } else {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) out[k] = cb * acc[k];
-        }
-        SpinorFmt<R>::store(make_buf((SV *)a.out[T.lat] + rhs * fs, fbytes), g.Vh, T.site, out);
-        if (EPI & EPI_DOTY) {
-            cx<R> yv[12];
-            SpinorFmt<R>::load(make_buf((const SV *)a.y[T.lat] + rhs * fs, fbytes), g.Vh, T.site, yv);
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                cx<R> d = cjmul(yv[k], out[k]);
-                q0 += d.re;
-                q1 += d.im;
-            }
-        }
-        if (EPI & EPI_NORM) {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) q2 += out[k].re * out[k].re + out[k].im * out[k].im;
+            link_load<LK>(gauge, Vh, (mu * 2 + par) * LK::NC * Vh * LK::ESZ, i, U);
         }
     }
-    if (EPI & (EPI_DOTY | EPI_DOTX_NORM | EPI_NORM)) {
-        double s0 = wave_sum((double)q0), s1 = wave_sum((double)q1), s2 = wave_sum((double)q2);
-        if (threadIdx.x % FL_WAVE == 0) {
-            const int ns = a.nsys, nb = a.B.nsb_max;
-            if (EPI & (EPI_DOTY | EPI_DOTX_NORM)) {
-                a.partial[pidx(a.slot0, ns, T.sys, nb, T.sb)] = s0;
-                a.partial[pidx(a.slot0 + 1, ns, T.sys, nb, T.sb)] = s1;
+};
+
+// checkerboard index of the backward neighbour x - mu of site (p, i)
+__device__ __forceinline__ int back_neighbour(const LatGeom &g, const Coord &c, int mu)
+{
+    const int Lh0 = g.Lh0, Ly = g.L[1], Lz = g.L[2], Lt = g.L[3], xh = c.x >> 1;
+    if (mu == 0) {
+        int xb = (c.x == 0) ? g.L[0] - 1 : c.x - 1;
+        return (xb >> 1) + Lh0 * c.rest;
+    } else if (mu == 1) {
+        int yb = (c.y == 0) ? Ly - 1 : c.y - 1;
+        return xh + Lh0 * (yb + Ly * (c.z + Lz * c.t));
+    } else if (mu == 2) {
+        int zb = (c.z == 0) ? Lz - 1 : c.z - 1;
+        return xh + Lh0 * (c.y + Ly * (zb + Lz * c.t));
+    }
+    int tb = (c.t == 0) ? Lt - 1 : c.t - 1;
+    return xh + Lh0 * (c.y + Ly * (c.z + Lz * tb));
+}
+
+template <typename R, class LK, bool DAG, int EPI, bool SLINK>
+__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_dslash_lds(DslashArgs a)
+{
+    typedef typename SpinorFmt<R>::V SV;
+    typedef typename LK::V LV;
+    constexpr int NCS = SpinorFmt<R>::NC;
+    extern __shared__ unsigned char smem[];
+    TileInfo T = tile_info(a.B);
+    const LatGeom &g = a.B.lat[T.lat];
+    const int Vh = g.Vh;
+    const int lane = threadIdx.x % FL_WAVE;
+    const int wave = threadIdx.x / FL_WAVE;
+    const int i0 = T.sb * FL_WAVE;
+    const int plane = g.Lh0 * g.L[1];  // sites of one (z, t) plane
+    const int wlo = (i0 / plane) * plane;
+    const int wsz = min(Vh, (min(i0 + FL_WAVE, Vh) - 1) / plane * plane + plane) - wlo;
+    const int wsmax = a.wsmax;
+    SV *win = (SV *)smem + (size_t)wave * NCS * wsmax;
+    LV *lk = (LV *)((SV *)smem + (size_t)a.B.RT * NCS * wsmax);
+    const bool live = T.valid_rhs && !(a.mask && !a.mask[T.sys]);
+    const int rhs = __builtin_amdgcn_readfirstlane(T.valid_rhs ? T.rhs : 0);
+    const size_t fs = (size_t)NCS * Vh;
+    const unsigned fbytes = (unsigned)(fs * sizeof(SV));
+    const Buf gbuf = make_buf(a.gauge[T.lat], (unsigned)(8u * LK::NC * LK::ESZ * (unsigned)Vh));
+    Buf ibuf = make_buf((const SV *)a.in[T.lat] + rhs * fs, fbytes);
+    if (SLINK) {
+        // the 8 links (4 forward at the site, 4 backward at the neighbour) of
+        // the block's 64 sites, shared by all its right-hand sides
+        for (int k = threadIdx.x; k < 8 * FL_WAVE; k += blockDim.x) {
+            const int dslot = k / FL_WAVE, s = k % FL_WAVE, mu = dslot >> 1;
+            const int site = i0 + s;
+            LV v[LK::NC];
+            if (site < Vh) {
+                int idx = site, par = a.par;
+                if (dslot & 1) {
+                    Coord c = cb_coords(g, a.par, site);
+                    idx = back_neighbour(g, c, mu);
+                    par = 1 - a.par;
+                }
+#pragma unroll
+                for (int cc = 0; cc < LK::NC; ++cc)
+                    v[cc] = LK::buf_get(gbuf, idx * LK::ESZ, ((mu * 2 + par) * LK::NC + cc) * Vh * LK::ESZ);
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < LK::NC; ++cc) v[cc] = LV{};
             }
-            if (EPI & (EPI_DOTX_NORM | EPI_NORM))
-                a.partial[pidx(a.slot0 + 2, ns, T.sys, nb, T.sb)] = s2;
+#pragma unroll
+            for (int cc = 0; cc < LK::NC; ++cc) lk[(dslot * LK::NC + cc) * FL_WAVE + s] = v[cc];
         }
+    }
+    if (live) {
+        for (int j = lane; j < wsz; j += FL_WAVE)
+#pragma unroll
+            for (int c = 0; c < NCS; ++c) {
+                v4f v = buf_ld16(ibuf, (wlo + j) * 16, c * Vh * 16);
+                SV o;
+                __builtin_memcpy(&o, &v, 16);
+                win[c * wsmax + j] = o;
+            }
+    }
+    __syncthreads();
+    if (!live) return;
+    R q0 = 0, q1 = 0, q2 = 0;
+    if (T.valid_site) {
+        Coord c = cb_coords(g, a.par, T.site);
+        LdsSrc<R, LK, SLINK> src;
+        src.in = ibuf;
+        src.gauge = gbuf;
+        src.Vh = Vh;
+        src.wlo = wlo;
+        src.wsz = wsz;
+        src.wsmax = wsmax;
+        src.p = a.par;
+        src.lane = lane;
+        src.win = win;
+        src.lk = lk;
+        cx<R> acc[12];
+        hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
+        epilogue<R, EPI>(a, T, g, rhs, acc, q0, q1, q2);
+    }
+    reduce_partials<EPI>(a, T, q0, q1, q2);
+}
+
+template <typename R, class LK>
+size_t dslash_lds_bytes_t(int RT, int wsmax, int lds)
+{
+    size_t b = (size_t)RT * SpinorFmt<R>::NC * wsmax * 16;
+    if (lds == 2) b += (size_t)8 * LK::NC * FL_WAVE * sizeof(typename LK::V);
+    return b;
+}
+
+template <typename R, class LK, bool DAG, int EPI>
+void launch_one(const DslashArgs &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (a.lds == 0) {
+        hipLaunchKernelGGL((k_dslash<R, LK, DAG, EPI>), grid, block, 0, s, a);
+    } else {
+        size_t shm = dslash_lds_bytes_t<R, LK>(a.B.RT, a.wsmax, a.lds);
+        if (a.lds == 2)
+            hipLaunchKernelGGL((k_dslash_lds<R, LK, DAG, EPI, true>), grid, block, shm, s, a);
+        else
+            hipLaunchKernelGGL((k_dslash_lds<R, LK, DAG, EPI, false>), grid, block, shm, s, a);
     }
 }
 
@@ -106,18 +272,12 @@ template <typename R, class LK, bool DAG>
 void dispatch_epi(const DslashArgs &a, int epi, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (epi) {
-    case EPI_PLAIN: hipLaunchKernelGGL((k_dslash<R, LK, DAG, EPI_PLAIN>), grid, block, 0, s, a); break;
-    case EPI_XPAY: hipLaunchKernelGGL((k_dslash<R, LK, DAG, EPI_XPAY>), grid, block, 0, s, a); break;
-    case EPI_XPAY | EPI_NORM:
-        hipLaunchKernelGGL((k_dslash<R, LK, DAG, EPI_XPAY | EPI_NORM>), grid, block, 0, s, a);
-        break;
-    case EPI_XPAY | EPI_DOTY:
-        hipLaunchKernelGGL((k_dslash<R, LK, DAG, EPI_XPAY | EPI_DOTY>), grid, block, 0, s, a);
-        break;
-    case EPI_XPAY | EPI_DOTX_NORM:
-        hipLaunchKernelGGL((k_dslash<R, LK, DAG, EPI_XPAY | EPI_DOTX_NORM>), grid, block, 0, s, a);
-        break;
-    case EPI_NORM: hipLaunchKernelGGL((k_dslash<R, LK, DAG, EPI_NORM>), grid, block, 0, s, a); break;
+    case EPI_PLAIN: launch_one<R, LK, DAG, EPI_PLAIN>(a, grid, block, s); break;
+    case EPI_XPAY: launch_one<R, LK, DAG, EPI_XPAY>(a, grid, block, s); break;
+    case EPI_XPAY | EPI_NORM: launch_one<R, LK, DAG, EPI_XPAY | EPI_NORM>(a, grid, block, s); break;
+    case EPI_XPAY | EPI_DOTY: launch_one<R, LK, DAG, EPI_XPAY | EPI_DOTY>(a, grid, block, s); break;
+    case EPI_XPAY | EPI_DOTX_NORM: launch_one<R, LK, DAG, EPI_XPAY | EPI_DOTX_NORM>(a, grid, block, s); break;
+    case EPI_NORM: launch_one<R, LK, DAG, EPI_NORM>(a, grid, block, s); break;
     default: break;
     }
 }
@@ -132,6 +292,17 @@ void dispatch_dag(const DslashArgs &a, bool dag, int epi, dim3 grid, dim3 block,
 }
 
 }  // namespace
+
+size_t dslash_lds_bytes(LinkFormat fmt, int RT, int wsmax, int lds)
+{
+    if (lds == 0) return 0;
+    switch (fmt) {
+    case LINK_F64_R18: return dslash_lds_bytes_t<double, LinkF64R18>(RT, wsmax, lds);
+    case LINK_F32_R18: return dslash_lds_bytes_t<float, LinkF32R18>(RT, wsmax, lds);
+    case LINK_F32_R12: return dslash_lds_bytes_t<float, LinkF32R12>(RT, wsmax, lds);
+    default: return dslash_lds_bytes_t<float, LinkBF16R12>(RT, wsmax, lds);
+    }
+}
 
 bool dslash_epi_supported(int epi)
 {

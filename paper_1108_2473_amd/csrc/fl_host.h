@@ -36,9 +36,14 @@ struct DslashArgs {
     const void *y[FL_MAXLAT];
     const void *gauge[FL_MAXLAT];
     double ca[FL_MAXLAT], cb[FL_MAXLAT];
+    int lds;    // 0: neighbours from memory; 1: x/y neighbours from an LDS window;
+                // 2: also the workgroup's links staged in LDS once
+    int wsmax;  // LDS window length in sites (64 + 2 * max Lx/2), set by the launcher
 };
 
 bool dslash_epi_supported(int epi);
+// LDS bytes the staged kernel needs for RT right-hand sides
+size_t dslash_lds_bytes(LinkFormat fmt, int RT, int wsmax, int lds);
 void launch_dslash(LinkFormat fmt, const DslashArgs &a, bool dag, int epi, hipStream_t s);
 
 // per-system Krylov state kept on the device
@@ -226,7 +231,12 @@ struct fl_ctx {
     ProfSlot prof[FL_PROF_NKERNELS];
     int tune_rt[4] = {0, 0, 0, 0};  // per LinkFormat; 0: heuristic
     int tune_g[4] = {0, 0, 0, 0};
+    int tune_lds[4] = {-1, -1, -1, -1};  // LDS staging mode; -1: built-in choice
+    size_t max_lds = 65536;              // LDS bytes a workgroup may use on this device
 };
+
+// LDS staging mode and window length for a hopping launch over batch B
+void dslash_config(const fl_ctx *c, LinkFormat fmt, DslashArgs &a);
 
 fl_status set_err(fl_ctx *c, fl_status st, const std::string &msg);
 fl_status hip_check(fl_ctx *c, hipError_t e, const char *what);

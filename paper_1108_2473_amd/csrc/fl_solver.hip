@@ -71,6 +71,7 @@ struct Solver {
             a.ca[l] = ca;
             a.cb[l] = cbv ? cbv[l] : 1.0;
         }
+        dslash_config(c0, f, a);
         if (prof) prof_begin(c0, FL_PROF_DSLASH);
         launch_dslash(f, a, dag, epi, st);
         if (prof) prof_end(c0, FL_PROF_DSLASH, 0.0);

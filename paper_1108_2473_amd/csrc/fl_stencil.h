@@ -89,10 +89,14 @@ struct PtrSrc {
     const typename SpinorFmt<R>::V *in;
     const typename LK::V *gauge;
     int Vh;
-    __device__ __forceinline__ void spinor(int i, cx<R> s[12]) const { SpinorFmt<R>::load(in, Vh, i, s); }
+    template <int MU>
+    __device__ __forceinline__ void spinor(int i, cx<R> s[12]) const
+    {
+        SpinorFmt<R>::load(in, Vh, i, s);
+    }
     __device__ __forceinline__ void link(int mu, int par, int i, cx<R> U[3][3]) const
     {
-        LK::load(gauge + (size_t)(mu * 2 + par) * LK::NC * Vh, Vh, i, U);
+        link_load<LK>(gauge + (size_t)(mu * 2 + par) * LK::NC * Vh, Vh, i, U);
     }
 };
 
@@ -100,10 +104,14 @@ template <typename R, class LK>
 struct BufSrc {
     Buf in, gauge;
     int Vh;
-    __device__ __forceinline__ void spinor(int i, cx<R> s[12]) const { SpinorFmt<R>::load(in, Vh, i, s); }
+    template <int MU>
+    __device__ __forceinline__ void spinor(int i, cx<R> s[12]) const
+    {
+        SpinorFmt<R>::load(in, Vh, i, s);
+    }
     __device__ __forceinline__ void link(int mu, int par, int i, cx<R> U[3][3]) const
     {
-        LK::load(gauge, Vh, (mu * 2 + par) * LK::NC * Vh * LK::ESZ, i, U);
+        link_load<LK>(gauge, Vh, (mu * 2 + par) * LK::NC * Vh * LK::ESZ, i, U);
     }
 };
 
@@ -114,13 +122,13 @@ __device__ __forceinline__ void hop_dir(int p, int i, int nf, int nb, R sf, R sb
     constexpr int SB = DAG ? -1 : 1;
     cx<R> psi[12], h[6], w[6], U[3][3];
     // forward hop: U_mu(x) psi(x + mu), link stored with the output parity
-    src.spinor(nf, psi);
+    src.template spinor<MU>(nf, psi);
     project<MU, SF>(psi, h);
     src.link(MU, p, i, U);
     link_mul(U, h, sf, w);
     accumulate<MU, SF>(acc, w);
     // backward hop: U_mu(x - mu)^+ psi(x - mu), link stored at the neighbour
-    src.spinor(nb, psi);
+    src.template spinor<MU>(nb, psi);
     project<MU, SB>(psi, h);
     src.link(MU, 1 - p, nb, U);
     link_adj_mul(U, h, sb, w);
