@@ -380,3 +380,49 @@ def loops_stochastic_multi(lattices, noises, gammas, lp: SolverParams = None, hp
     if st != 0:
         raise FloopError(st, lib().fl_last_error(lattices[0]._h).decode())
     return outs
+
+
+def _loop_fn_class():
+    import torch
+
+    class LoopFn(torch.autograd.Function):
+        """Exact loops L[ngamma][nt][Vs] = fl_loops_exact(kappa, U) as a differentiable
+        function of kappa (0-dim float64 tensor) and the links U (complex128
+        [4][V][3][3]); the backward pass is the adjoint gradient fl_loops_grad
+        (gamma_5-hermiticity gives the adjoint solutions from the forward ones).
+        PyTorch's complex convention is used throughout: the incoming gradient w
+        of L defines dLoss = Re sum conj(w) dL, and U.grad = dLoss/dRe U + i dLoss/dIm U.
+        """
+
+        @staticmethod
+        def forward(ctx, kappa, U, lattice, t0, gammas, params):
+            lattice.set_gauge(U.detach())
+            lattice.set_kappa(float(kappa.detach()))
+            L = lattice.loops_exact(t0, gammas, params, device=U.is_cuda)
+            if not U.is_cuda:
+                L = torch.from_numpy(L)
+            ctx.lattice, ctx.t0, ctx.gammas, ctx.params = lattice, list(t0), list(gammas), params
+            ctx.save_for_backward(kappa, U)
+            return L
+
+        @staticmethod
+        def backward(ctx, gL):
+            kappa, U = ctx.saved_tensors
+            lat = ctx.lattice
+            lat.set_gauge(U.detach())
+            lat.set_kappa(float(kappa))
+            w = gL.detach().to(torch.complex128).contiguous()
+            if not U.is_cuda:
+                w = w.cpu().numpy()
+            dU, dk = lat.loops_grad(ctx.t0, ctx.gammas, w, ctx.params)
+            if not U.is_cuda:
+                dU = torch.from_numpy(dU)
+            gk = torch.tensor(dk, dtype=kappa.dtype, device=kappa.device)
+            return gk, dU, None, None, None, None
+
+    return LoopFn
+
+
+def loops_exact_autograd(kappa, U, lattice, t0, gammas, params: SolverParams = None):
+    """Differentiable exact loops (see LoopFn)."""
+    return _loop_fn_class().apply(kappa, U, lattice, t0, gammas, params or SolverParams())

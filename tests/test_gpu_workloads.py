@@ -1,0 +1,138 @@
+"""GPU parity at the workloads' full sizes: the 16^3x32 stochastic lattice, the
+uneven three-lattice truncated-solver batch, and the 12^3x24 gradient, each
+checked on sampled outputs the oracle computes one by one or through
+properties that hold at any size (finite differences, batch independence)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth_inputs as S
+
+pytestmark = pytest.mark.gpu
+
+GAMMAS = [0, 15, 1, 2, 4, 8]
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_1108_2473_amd as fl
+    fl.lib()
+    return fl
+
+
+def lattice(F, name, kappa=None):
+    W = S.WORKLOADS[name]
+    U = S.random_links(W["dims"], W["eps"], W["link_seed"])
+    lat = F.Lattice(W["dims"], W["bc_t"])
+    lat.set_gauge(U)
+    lat.set_kappa(kappa if kappa is not None else W["kappa"])
+    return lat, U, W
+
+
+def test_stochastic_16x16x16x32_one_timeslice(F):
+    """16^3x32, eps 0.6, kappa 0.1596 (~400 FP64 BiCGStab iterations): a time-diluted
+    Z4 source on timeslice 3 through the whole stochastic path (noise, prepare, mixed
+    precision CGNR to 1e-12, reconstruction, contraction) against the oracle."""
+    lat, U, W = lattice(F, "stoch_16x16x16x32")
+    q = F.NoiseParams(noise=F.NOISE_Z4, seed=W["noise_seed"], r0=7, n_lp=1, dilution=F.DIL_TIME,
+                      t_begin=3, t_end=4)
+    got = lat.loops_stochastic(q, GAMMAS, lp=F.SolverParams(tol=1e-12, solver=F.SOLVER_CGNR))
+    want = O.loops_stochastic(U, W["dims"], W["bc_t"], W["kappa"], O.NOISE_Z4, W["noise_seed"], 7, 1,
+                              O.DIL_TIME, 3, 4, GAMMAS, tol=1e-13)
+    err = np.abs(got - want).max() / np.abs(want[0]).max()
+    assert err <= 1e-10, err
+
+
+def test_solver_16x16x16x32_stopping_rule(F):
+    """Batched mixed-precision solves (BiCGStab and CGNR) of spin-colour-time
+    diluted sources at 16^3x32 meet |Dx-b|/|b| <= 1e-12, recomputed by the oracle."""
+    lat, U, W = lattice(F, "stoch_16x16x16x32")
+    xi = O.noise(O.NOISE_Z4, W["noise_seed"], 0, W["dims"])
+    Vs = 16 ** 3
+    b = np.zeros((3,) + xi.shape, complex)
+    for k, (t, s, c) in enumerate([(0, 0, 0), (11, 2, 1), (31, 3, 2)]):
+        b[k, Vs * t:Vs * (t + 1), s, c] = xi[Vs * t:Vs * (t + 1), s, c]
+    for solver in (F.SOLVER_BICGSTAB, F.SOLVER_CGNR):
+        x, info = lat.solve(b, F.SolverParams(tol=1e-12, solver=solver))
+        r = b - O.apply_D(U, x, W["dims"], W["bc_t"], W["kappa"])
+        rel = np.linalg.norm(r.reshape(3, -1), axis=1) / np.linalg.norm(b.reshape(3, -1), axis=1)
+        assert np.all(rel <= 1.05e-12), (solver, rel)
+
+
+def test_uneven_tsm_batch(F):
+    """8^4, 12^3x24 and 16^3x32 (eps 0.4/0.5/0.6, kappa 0.14) in one batch: 64
+    complex-Z2 LP solves truncated at 1e-3 plus 4 FP64-corrected HP vectors each,
+    all Gamma.  Each lattice's estimate equals a separate single-lattice run bit
+    for bit, and the HP ensemble's estimate on 8^4 equals the oracle's."""
+    names = ["tsm_8x8x8x8", "tsm_12x12x12x24", "tsm_16x16x16x32"]
+    lats = [lattice(F, n) for n in names]
+    lp = F.SolverParams(tol=1e-3, truncated=True)
+    hp = F.SolverParams(tol=1e-12)
+    qs = [F.NoiseParams(noise=F.NOISE_CZ2, seed=W["noise_seed"], r0=0, n_lp=64, n_hp=4, dilution=0,
+                        t_begin=0, t_end=W["dims"][3]) for (_, _, W) in lats]
+    multi = F.loops_stochastic_multi([l for (l, _, _) in lats], qs, GAMMAS, lp, hp)
+    single = lats[0][0].loops_stochastic(qs[0], GAMMAS, lp=lp, hp=hp)
+    assert np.array_equal(single, multi[0])
+    for m in multi:
+        assert np.all(np.isfinite(m))
+        assert np.abs(m[0].imag).max() < 1e-2 * np.abs(m[0].real).max() + 1.0
+    lat8, U8, W8 = lats[0]
+    q = F.NoiseParams(noise=F.NOISE_CZ2, seed=W8["noise_seed"], r0=64, n_lp=4, dilution=0, t_begin=0,
+                      t_end=8)
+    got = lat8.loops_stochastic(q, GAMMAS, lp=hp)
+    want = O.loops_stochastic(U8, W8["dims"], W8["bc_t"], W8["kappa"], O.NOISE_CZ2, W8["noise_seed"], 64, 4,
+                              0, 0, 8, GAMMAS, tol=1e-13)
+    assert np.abs(got - want).max() / np.abs(want[0]).max() <= 1e-10
+
+
+def test_gradient_12x12x12x24_finite_differences(F):
+    """12^3x24, kappa 0.14, eps 0.5: gradients of sum_x Re L_Gamma(x) (Gamma = 1, g5)
+    over a site subset W of timeslice 0 with respect to kappa and the links, against
+    central finite differences (h = 1e-5) on 20 random Lie directions."""
+    lat, U, W = lattice(F, "grad_12x12x12x24")
+    dims = W["dims"]
+    Vs = dims[0] * dims[1] * dims[2]
+    rng = np.random.Generator(np.random.PCG64(4000))
+    sites = rng.choice(Vs, 8, replace=False)
+    w = np.zeros((2, 1, Vs), complex)
+    w[:, 0, sites] = 1.0
+    prm = F.SolverParams(tol=1e-13, inner_prec=F.PREC_F64, gauge_reals=18)
+    dU, dk = lat.loops_grad([0], [0, 15], w, prm)
+    V = S.volume(dims)
+
+    def Fval(Ux, kap):
+        lat.set_gauge(Ux)
+        lat.set_kappa(kap)
+        L = lat.loops_exact_sites(sites, [0, 15], prm)
+        return float(L.real.sum())
+
+    h = 1e-5
+    X = S.random_su3_directions(20 * 4 * V, 4001).reshape(20, 4, V, 3, 3)
+    for k in range(20):
+        w_, Q = np.linalg.eigh(X[k])
+        E = lambda t: np.einsum("...ij,...j,...kj->...ik", Q, np.exp(1j * t * w_), Q.conj())
+        fd = (Fval(E(h) @ U, W["kappa"]) - Fval(E(-h) @ U, W["kappa"])) / (2 * h)
+        pred = float(np.sum((dU.conj() * (1j * X[k] @ U)).real))
+        assert abs(fd - pred) <= 1e-6 * max(1.0, abs(pred)), (k, fd, pred)
+    fdk = (Fval(U, W["kappa"] + h) - Fval(U, W["kappa"] - h)) / (2 * h)
+    assert abs(fdk - dk) <= 1e-6 * max(1.0, abs(dk)), (fdk, dk)
+
+
+def test_autograd_loopfn_matches_oracle(F):
+    """torch.autograd through LoopFn: the gradient of a real loss of the loops with
+    respect to kappa and U equals the oracle's adjoint gradient."""
+    import torch
+    dims = (4, 2, 2, 4)
+    W = dict(eps=0.5, kappa=0.13)
+    U = S.random_links(dims, 0.5, 4100)
+    lat = F.Lattice(dims, -1)
+    kap = torch.tensor(0.13, dtype=torch.float64, requires_grad=True)
+    Ut = torch.from_numpy(U).cuda().requires_grad_(True)
+    L = F.loops_exact_autograd(kap, Ut, lat, [1], [0, 15, 8], F.SolverParams(tol=1e-13))
+    coef = torch.tensor([1.0, 0.5, -0.3], dtype=torch.float64, device="cuda")
+    loss = (coef[:, None, None] * (L.real + 2.0 * L.imag)).sum()
+    loss.backward()
+    w = (coef.cpu().numpy()[:, None, None] * (1.0 + 2.0j)) * np.ones((3, 1, 16))
+    dUo, dko = O.loops_grad(U, dims, -1, 0.13, [1], [0, 15, 8], w, tol=1e-14)
+    assert abs(kap.grad.item() - dko) <= 1e-9 * abs(dko)
+    assert np.abs(Ut.grad.cpu().numpy() - dUo).max() <= 1e-9 * np.abs(dUo).max()
