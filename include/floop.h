@@ -64,7 +64,7 @@ typedef enum {
 
 typedef enum { FL_HOST = 0, FL_DEVICE = 1 } fl_where;
 
-typedef enum { FL_PREC_F64 = 0, FL_PREC_F32 = 1, FL_PREC_BF16 = 2 } fl_prec;
+typedef enum { FL_PREC_F64 = 0, FL_PREC_F32 = 1, FL_PREC_BF16 = 2, FL_PREC_H16 = 3 } fl_prec;
 
 typedef enum { FL_SOLVER_BICGSTAB = 0, FL_SOLVER_CGNR = 1 } fl_solver_kind;
 
@@ -84,12 +84,19 @@ enum { FL_DIL_TIME = 1, FL_DIL_SPIN = 2, FL_DIL_COLOUR = 4, FL_DIL_EVENODD = 8,
  *  max_iter    Krylov iterations per right-hand side, all cycles included.
  *  inner_prec  precision of the Krylov iteration.  FL_PREC_F64 runs the
  *              whole solve in FP64; F32 runs FP32 vectors and links; BF16
- *              stores the links in bfloat16 (FP32 vectors and arithmetic).
- *              For F32/BF16 the FP64 residual b - Dx is recomputed and the
- *              iteration residual replaced whenever the latter has dropped
- *              by `delta` since the last replacement (reliable updates).
+ *              stores the links in bfloat16 (FP32 vectors and arithmetic);
+ *              H16 stores the iteration vectors as 16-bit fixed point with
+ *              one FP32 scale per site (52 bytes per site instead of 96) and
+ *              the links as 16-bit fixed point (12 reals, 24 bytes), with
+ *              FP32 arithmetic (the paper ran mixed-precision GPU solvers,
+ *              Sec. II; this is the narrowest storage offered here).
+ *              For F32/BF16/H16 the FP64 residual b - Dx is recomputed and
+ *              the iteration residual replaced whenever the latter has
+ *              dropped by `delta` since the last replacement (reliable
+ *              updates).
  *  gauge_reals 18 (full links) or 12 (rows 0 and 1; row 2 rebuilt as
- *              conj(row0 x row1)) for the F32/BF16 inner operator.
+ *              conj(row0 x row1)) for the F32 inner operator; BF16 and H16
+ *              need 12.
  *  delta       reliable-update trigger in (0, 1); 0 selects 0.1.
  *  truncated   1: low-precision (LP) solve of the truncated solver method:
  *              inner precision only, stops when the iteration's own

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FLOOP_LIB") or os.path.join(_HERE, "_lib", "libfloop.so")
 
 FL_HOST, FL_DEVICE = 0, 1
-PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
+PREC_F64, PREC_F32, PREC_BF16, PREC_H16 = 0, 1, 2, 3
 SOLVER_BICGSTAB, SOLVER_CGNR = 0, 1
 NOISE_Z4, NOISE_CZ2, NOISE_Z2 = 0, 1, 2
 DIL_TIME, DIL_SPIN, DIL_COLOUR, DIL_EVENODD, DIL_CUBIC = 1, 2, 4, 8, 16

@@ -96,12 +96,12 @@ fl_status check_params(fl_ctx *c, const fl_solver_params *p)
     if (!(p->tol > 0) || !std::isfinite(p->tol)) return set_err(c, FL_ERR_ARG, "tol must be > 0");
     if (p->solver != FL_SOLVER_BICGSTAB && p->solver != FL_SOLVER_CGNR)
         return set_err(c, FL_ERR_ARG, "unknown solver");
-    if (p->inner_prec < FL_PREC_F64 || p->inner_prec > FL_PREC_BF16)
+    if (p->inner_prec < FL_PREC_F64 || p->inner_prec > FL_PREC_H16)
         return set_err(c, FL_ERR_ARG, "unknown inner precision");
     if (p->gauge_reals != 18 && p->gauge_reals != 12) return set_err(c, FL_ERR_ARG, "gauge_reals must be 12 or 18");
     if (p->max_iter < 0 || p->batch < 0) return set_err(c, FL_ERR_ARG, "negative max_iter or batch");
-    if (p->inner_prec == FL_PREC_BF16 && p->gauge_reals != 12)
-        return set_err(c, FL_ERR_ARG, "bfloat16 links are stored with 12 reals");
+    if ((p->inner_prec == FL_PREC_BF16 || p->inner_prec == FL_PREC_H16) && p->gauge_reals != 12)
+        return set_err(c, FL_ERR_ARG, "bfloat16 and 16-bit fixed-point links are stored with 12 reals");
     if (p->inner_prec != FL_PREC_F64 && p->gauge_reals == 12 && !c->su3)
         return set_err(c, FL_ERR_ARG, "12-real links need SU(3) links; use gauge_reals = 18");
     return FL_OK;
@@ -153,10 +153,10 @@ fl_status norms64(fl_ctx *c, int nrhs, const void *fe, const void *fo, std::vect
     a.partial = part;
     a.slot0 = 0;
     a.f[0][0] = (void *)fe;
-    launch_blas(true, a, c->stream);
+    launch_blas(VEC_F64, a, c->stream);
     a.slot0 = 3;
     a.f[0][0] = (void *)fo;
-    launch_blas(true, a, c->stream);
+    launch_blas(VEC_F64, a, c->stream);
     std::vector<double> h(np);
     if ((e = hip_check(c, hipMemcpyAsync(h.data(), part, np * sizeof(double), hipMemcpyDeviceToHost, c->stream),
                        "download norms")))
@@ -294,7 +294,7 @@ void dslash_config(const fl_ctx *c, LinkFormat fmt, DslashArgs &a)
             if (plane % FL_WAVE == 0 && i0 >= plane) break;  // every block alike
         }
     }
-    a.wsmax = ws;
+    a.wsmax = (ws + 3) & ~3;  // 16-byte aligned windows for every site format
     int mode = c->tune_lds[fmt];
     // built-in (measured at 16^3x32): FP32 windows and staged links, FP64
     // windows only; a mode that does not fit the LDS falls back to the next
@@ -307,8 +307,7 @@ void *links(fl_ctx *c, LinkFormat fmt)
 {
     if (!c->have_gauge) return nullptr;
     if (!c->gauge[fmt]) {
-        size_t per = fmt == LINK_F64_R18 ? 144 : (fmt == LINK_F32_R18 ? 72 : (fmt == LINK_F32_R12 ? 48 : 24));
-        if (hipMalloc(&c->gauge[fmt], per * 4 * (size_t)c->V) != hipSuccess) {
+        if (hipMalloc(&c->gauge[fmt], link_bytes(fmt) * 4 * (size_t)c->V) != hipSuccess) {
             c->gauge[fmt] = nullptr;
             (void)hipGetLastError();
             return nullptr;
@@ -420,7 +419,7 @@ fl_status fl_destroy(fl_ctx *c)
     hipStreamSynchronize(c->stream);
     for (auto &b : c->pool)
         if (b.p) hipFree(b.p);
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < LINK_NFMT; ++k)
         if (c->gauge[k]) hipFree(c->gauge[k]);
     if (c->gauge_canon) hipFree(c->gauge_canon);
     for (auto &p : c->prof) prof_reset(p);
@@ -478,7 +477,7 @@ fl_status fl_set_gauge(fl_ctx *c, const double *U, fl_where where)
     for (double v : h) dev = std::max(dev, v);
     if (!std::isfinite(dev)) return set_err(c, FL_ERR_ARG, "gauge field holds non-finite values");
     c->su3 = dev <= 1e-10;
-    for (int k = 0; k < 4; ++k) c->gauge_ok[k] = false;
+    for (int k = 0; k < LINK_NFMT; ++k) c->gauge_ok[k] = false;
     c->have_gauge = true;
     if (!links(c, LINK_F64_R18)) return set_err(c, FL_ERR_NOMEM, "device allocation failed (links)");
     return hip_check(c, hipStreamSynchronize(c->stream), "pack links");
@@ -588,11 +587,11 @@ fl_status fl_solve(fl_ctx *c, const double *b, double *x, int nrhs, const fl_sol
             a.f[0][0] = he;
             a.f[1][0] = be;
             a.f[2][0] = he;
-            launch_blas(true, a, c->stream);
+            launch_blas(VEC_F64, a, c->stream);
             a.f[0][0] = ho;
             a.f[1][0] = bo;
             a.f[2][0] = ho;
-            launch_blas(true, a, c->stream);
+            launch_blas(VEC_F64, a, c->stream);
         }
         std::vector<double> r2;
         if ((e = norms64(c, n, he, ho, r2))) return e;
@@ -1124,9 +1123,11 @@ static fl_status fmt_of(fl_ctx *c, int prec, int gauge_reals, LinkFormat *fmt)
         *fmt = gauge_reals == 18 ? LINK_F32_R18 : LINK_F32_R12;
     else if (prec == FL_PREC_BF16 && gauge_reals == 12)
         *fmt = LINK_BF16_R12;
+    else if (prec == FL_PREC_H16 && gauge_reals == 12)
+        *fmt = LINK_Q16_R12;
     else
         return set_err(c, FL_ERR_ARG, "unsupported precision / link storage");
-    if ((*fmt == LINK_F32_R12 || *fmt == LINK_BF16_R12) && !c->su3)
+    if (*fmt != LINK_F64_R18 && *fmt != LINK_F32_R18 && !c->su3)
         return set_err(c, FL_ERR_ARG, "12-real links need SU(3) links");
     return FL_OK;
 }
@@ -1136,8 +1137,8 @@ static fl_status bench_impl(fl_ctx *c, LinkFormat fmt, int nrhs, int nrep, int n
 {
     hipSetDevice(c->device);
     hipStream_t st = c->stream;
-    const size_t sb = (fmt == LINK_F64_R18) ? 192 : 96;
-    const size_t lb = fmt == LINK_F64_R18 ? 144 : (fmt == LINK_F32_R18 ? 72 : (fmt == LINK_F32_R12 ? 48 : 24));
+    const size_t sb = vec_site_bytes(vec_format(fmt));
+    const size_t lb = link_bytes(fmt);
     const size_t fbytes = (size_t)nrhs * c->Vh * sb, gbytes = lb * 4 * (size_t)c->V;
     void *src = links(c, fmt);
     if (!src) return set_err(c, FL_ERR_NOMEM, "device allocation failed (links)");
@@ -1233,6 +1234,8 @@ fl_status fl_set_tile(fl_ctx *c, int prec, int gauge_reals, int rt, int group, i
         fmt = gauge_reals == 18 ? LINK_F32_R18 : LINK_F32_R12;
     else if (prec == FL_PREC_BF16 && gauge_reals == 12)
         fmt = LINK_BF16_R12;
+    else if (prec == FL_PREC_H16 && gauge_reals == 12)
+        fmt = LINK_Q16_R12;
     else
         return set_err(c, FL_ERR_ARG, "unsupported precision / link storage");
     c->tune_rt[fmt] = rt;

@@ -19,13 +19,11 @@
 namespace {
 
 // per-wave buffer view of right-hand side `rhs` of a field stored as
-// SpinorFmt<R> (one resource per field, built in scalar registers)
-template <typename R>
+// SpinorFmt<S> (one resource per field, built in scalar registers)
+template <typename S>
 __device__ __forceinline__ Buf fbuf(const void *base, const LatGeom &g, int rhs)
 {
-    const size_t fs = (size_t)SpinorFmt<R>::NC * g.Vh;
-    const unsigned bytes = (unsigned)(fs * sizeof(typename SpinorFmt<R>::V));
-    return make_buf((const typename SpinorFmt<R>::V *)base + rhs * fs, bytes);
+    return spinor_buf<S>(base, g.Vh, rhs);
 }
 
 template <typename R>
@@ -34,16 +32,18 @@ __device__ __forceinline__ cx<R> cpx_of(const double *v)
     return cx<R>{(R)v[0], (R)v[1]};
 }
 
-template <typename R, int OP>
-__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_blas(BlasArgs a)
+// S: storage format of the iteration vectors, arithmetic in SpinorFmt<S>::R
+template <typename S, int OP>
+__global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024) void k_blas(BlasArgs a)
 {
+    typedef typename SpinorFmt<S>::R R;
     TileInfo T = tile_info(a.B);
     if (!T.valid_rhs) return;
     if (a.mask && !a.mask[T.sys]) return;
     const LatGeom &g = a.B.lat[T.lat];
     const int l = T.lat, i = T.site, Vh = g.Vh;
     const int rhs = __builtin_amdgcn_readfirstlane(T.rhs);
-    typedef SpinorFmt<R> F;
+    typedef SpinorFmt<S> F;
     typedef SpinorFmt<double> F64;
     R q0 = 0, q1 = 0, q2 = 0;
     if (T.valid_site) {
@@ -51,59 +51,62 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_blas(BlasArgs a
             const SysState &st = a.st[T.sys];
             cx<R> al = cpx_of<R>(st.alpha);
             cx<R> r[12], v[12];
-            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, r);
-            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, v);
+            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, r);
+            F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, v);
 #pragma unroll
             for (int k = 0; k < 12; ++k) r[k] = cmsub(r[k], al, v[k]);
-            F::store(fbuf<R>(a.f[2][l], g, rhs), Vh, i, r);
+            F::store(fbuf<S>(a.f[2][l], g, rhs), Vh, i, r);
         } else if (OP == OP_BICG_XR) {
             const SysState &st = a.st[T.sys];
             cx<R> al = cpx_of<R>(st.alpha), om = cpx_of<R>(st.omega);
             cx<R> x[12], p[12], s[12], t[12], r0[12];
-            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, x);
-            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, p);
-            F::load(fbuf<R>(a.f[2][l], g, rhs), Vh, i, s);
-            F::load(fbuf<R>(a.f[3][l], g, rhs), Vh, i, t);
-            F::load(fbuf<R>(a.f[5][l], g, rhs), Vh, i, r0);
+            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, x);
+            F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, p);
+            F::load(fbuf<S>(a.f[2][l], g, rhs), Vh, i, s);
+            F::load(fbuf<S>(a.f[3][l], g, rhs), Vh, i, t);
+            F::load(fbuf<S>(a.f[5][l], g, rhs), Vh, i, r0);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 x[k] = cmad(cmad(x[k], al, p[k]), om, s[k]);
                 s[k] = cmsub(s[k], om, t[k]);  // new r
+            }
+            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, x);
+            F::store(fbuf<S>(a.f[4][l], g, rhs), Vh, i, s);  // reductions of the stored values
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
                 cx<R> d = cjmul(r0[k], s[k]);
                 q0 += d.re;
                 q1 += d.im;
                 q2 += s[k].re * s[k].re + s[k].im * s[k].im;
             }
-            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, x);
-            F::store(fbuf<R>(a.f[4][l], g, rhs), Vh, i, s);
         } else if (OP == OP_BICG_P) {
             const SysState &st = a.st[T.sys];
             cx<R> be = cpx_of<R>(st.beta), om = cpx_of<R>(st.omega);
             cx<R> p[12], r[12], v[12];
-            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, p);
-            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, r);
-            F::load(fbuf<R>(a.f[2][l], g, rhs), Vh, i, v);
+            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
+            F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, r);
+            F::load(fbuf<S>(a.f[2][l], g, rhs), Vh, i, v);
 #pragma unroll
             for (int k = 0; k < 12; ++k) p[k] = cmad(r[k], be, cmsub(p[k], om, v[k]));
-            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, p);
+            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
         } else if (OP == OP_HI_TO_LO) {
             cx<double> h[12];
             cx<R> lo[12], r0[12];
             F64::load(fbuf<double>(a.f[1][l], g, rhs), Vh, i, h);
 #pragma unroll
             for (int k = 0; k < 12; ++k) lo[k] = cx<R>{(R)h[k].re, (R)h[k].im};
-            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, lo);
+            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, lo);
             if (a.flag) {
-                F::store(fbuf<R>(a.f[2][l], g, rhs), Vh, i, lo);
-                F::store(fbuf<R>(a.f[3][l], g, rhs), Vh, i, lo);
+                F::store(fbuf<S>(a.f[2][l], g, rhs), Vh, i, lo);
+                F::store(fbuf<S>(a.f[3][l], g, rhs), Vh, i, lo);
                 cx<R> z[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) z[k] = cx<R>{(R)0, (R)0};
-                F::store(fbuf<R>(a.f[4][l], g, rhs), Vh, i, z);
+                F::store(fbuf<S>(a.f[4][l], g, rhs), Vh, i, z);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) r0[k] = lo[k];
             } else {
-                F::load(fbuf<R>(a.f[2][l], g, rhs), Vh, i, r0);
+                F::load(fbuf<S>(a.f[2][l], g, rhs), Vh, i, r0);
             }
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
@@ -116,14 +119,14 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_blas(BlasArgs a
             cx<double> h[12];
             cx<R> lo[12];
             F64::load(fbuf<double>(a.f[0][l], g, rhs), Vh, i, h);
-            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, lo);
+            F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, lo);
 #pragma unroll
             for (int k = 0; k < 12; ++k) h[k] = h[k] + cx<double>{(double)lo[k].re, (double)lo[k].im};
             F64::store(fbuf<double>(a.f[0][l], g, rhs), Vh, i, h);
             if (a.flag) {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) lo[k] = cx<R>{(R)0, (R)0};
-                F::store(fbuf<R>(a.f[1][l], g, rhs), Vh, i, lo);
+                F::store(fbuf<S>(a.f[1][l], g, rhs), Vh, i, lo);
             }
         } else if (OP == OP_SUB_HI) {
             cx<double> u[12], w[12];
@@ -134,66 +137,61 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_blas(BlasArgs a
             F64::store(fbuf<double>(a.f[0][l], g, rhs), Vh, i, u);
         } else if (OP == OP_NORM) {
             cx<R> f[12];
-            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, f);
+            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, f);
 #pragma unroll
             for (int k = 0; k < 12; ++k) q2 += f[k].re * f[k].re + f[k].im * f[k].im;
         } else if (OP == OP_ZERO) {
             cx<R> z[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) z[k] = cx<R>{(R)0, (R)0};
-            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, z);
+            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, z);
         } else if (OP == OP_CG_XR) {
             const R al = (R)a.st[T.sys].alpha[0];
             cx<R> x[12], r[12], p[12], q[12];
-            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, x);
-            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, r);
-            F::load(fbuf<R>(a.f[2][l], g, rhs), Vh, i, p);
-            F::load(fbuf<R>(a.f[3][l], g, rhs), Vh, i, q);
+            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, x);
+            F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, r);
+            F::load(fbuf<S>(a.f[2][l], g, rhs), Vh, i, p);
+            F::load(fbuf<S>(a.f[3][l], g, rhs), Vh, i, q);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 x[k] = cx<R>{fma(al, p[k].re, x[k].re), fma(al, p[k].im, x[k].im)};
                 r[k] = cx<R>{fma(-al, q[k].re, r[k].re), fma(-al, q[k].im, r[k].im)};
-                q2 += r[k].re * r[k].re + r[k].im * r[k].im;
             }
-            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, x);
-            F::store(fbuf<R>(a.f[1][l], g, rhs), Vh, i, r);
+            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, x);
+            F::store(fbuf<S>(a.f[1][l], g, rhs), Vh, i, r);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) q2 += r[k].re * r[k].re + r[k].im * r[k].im;
         } else if (OP == OP_CG_P) {
             const R be = (R)a.st[T.sys].beta[0];
             cx<R> p[12], z[12];
-            F::load(fbuf<R>(a.f[0][l], g, rhs), Vh, i, p);
-            F::load(fbuf<R>(a.f[1][l], g, rhs), Vh, i, z);
+            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
+            F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, z);
 #pragma unroll
             for (int k = 0; k < 12; ++k) p[k] = cx<R>{fma(be, p[k].re, z[k].re), fma(be, p[k].im, z[k].im)};
-            F::store(fbuf<R>(a.f[0][l], g, rhs), Vh, i, p);
+            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
         }
     }
     if (OP == OP_BICG_XR || OP == OP_HI_TO_LO || OP == OP_NORM || OP == OP_CG_XR) {
         double s0 = wave_sum((double)q0), s1 = wave_sum((double)q1), s2 = wave_sum((double)q2);
-        if (threadIdx.x % FL_WAVE == 0) {
-            const int ns = a.nsys, nb = a.B.nsb_max;
-            if (OP == OP_BICG_XR || OP == OP_HI_TO_LO) {
-                a.partial[pidx(a.slot0, ns, T.sys, nb, T.sb)] = s0;
-                a.partial[pidx(a.slot0 + 1, ns, T.sys, nb, T.sb)] = s1;
-            }
-            a.partial[pidx(a.slot0 + 2, ns, T.sys, nb, T.sb)] = s2;
-        }
+        constexpr int which = (OP == OP_BICG_XR || OP == OP_HI_TO_LO) ? 7 : 4;
+        write_partials(a.partial, a.slot0, a.nsys, T.sys, a.B.nsb_max, T.sb, s0, s1, s2, which);
     }
 }
 
-template <typename R>
+template <typename S>
 void dispatch(const BlasArgs &a, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (a.op) {
-    case OP_BICG_S: hipLaunchKernelGGL((k_blas<R, OP_BICG_S>), grid, block, 0, s, a); break;
-    case OP_BICG_XR: hipLaunchKernelGGL((k_blas<R, OP_BICG_XR>), grid, block, 0, s, a); break;
-    case OP_BICG_P: hipLaunchKernelGGL((k_blas<R, OP_BICG_P>), grid, block, 0, s, a); break;
-    case OP_HI_TO_LO: hipLaunchKernelGGL((k_blas<R, OP_HI_TO_LO>), grid, block, 0, s, a); break;
-    case OP_ACC_HI: hipLaunchKernelGGL((k_blas<R, OP_ACC_HI>), grid, block, 0, s, a); break;
-    case OP_SUB_HI: hipLaunchKernelGGL((k_blas<R, OP_SUB_HI>), grid, block, 0, s, a); break;
-    case OP_NORM: hipLaunchKernelGGL((k_blas<R, OP_NORM>), grid, block, 0, s, a); break;
-    case OP_ZERO: hipLaunchKernelGGL((k_blas<R, OP_ZERO>), grid, block, 0, s, a); break;
-    case OP_CG_XR: hipLaunchKernelGGL((k_blas<R, OP_CG_XR>), grid, block, 0, s, a); break;
-    case OP_CG_P: hipLaunchKernelGGL((k_blas<R, OP_CG_P>), grid, block, 0, s, a); break;
+    case OP_BICG_S: hipLaunchKernelGGL((k_blas<S, OP_BICG_S>), grid, block, 0, s, a); break;
+    case OP_BICG_XR: hipLaunchKernelGGL((k_blas<S, OP_BICG_XR>), grid, block, 0, s, a); break;
+    case OP_BICG_P: hipLaunchKernelGGL((k_blas<S, OP_BICG_P>), grid, block, 0, s, a); break;
+    case OP_HI_TO_LO: hipLaunchKernelGGL((k_blas<S, OP_HI_TO_LO>), grid, block, 0, s, a); break;
+    case OP_ACC_HI: hipLaunchKernelGGL((k_blas<S, OP_ACC_HI>), grid, block, 0, s, a); break;
+    case OP_SUB_HI: hipLaunchKernelGGL((k_blas<S, OP_SUB_HI>), grid, block, 0, s, a); break;
+    case OP_NORM: hipLaunchKernelGGL((k_blas<S, OP_NORM>), grid, block, 0, s, a); break;
+    case OP_ZERO: hipLaunchKernelGGL((k_blas<S, OP_ZERO>), grid, block, 0, s, a); break;
+    case OP_CG_XR: hipLaunchKernelGGL((k_blas<S, OP_CG_XR>), grid, block, 0, s, a); break;
+    case OP_CG_P: hipLaunchKernelGGL((k_blas<S, OP_CG_P>), grid, block, 0, s, a); break;
     default: break;
     }
 }
@@ -204,40 +202,15 @@ void dispatch(const BlasArgs &a, dim3 grid, dim3 block, hipStream_t s)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool finite_d(double v) { return v == v && v - v == 0.0; }
 
-__global__ __launch_bounds__(256) void k_scal(ScalArgs a)
+// one step of a system's scalar recurrence on a local copy of its state
+__device__ __forceinline__ void scal_step(const ScalArgs &a, const double P[6], SysState &s, int &act)
 {
-    const int sys = blockIdx.x;
-    if (a.mask) {
-        if (!a.mask[sys]) return;
-    } else if (!a.active[sys]) {
-        return;
-    }
-    int l = 0;
-    for (int k = 1; k < FL_MAXLAT; ++k)
-        if (k < a.B.nlat && sys >= a.B.lat[k].sys0) l = k;
-    const int nsb = a.B.lat[l].nsb, nb = a.B.nsb_max;
-    __shared__ double red[6][256];
-    for (int slot = 0; slot < 6; ++slot) {
-        double acc = 0;
-        for (int sb = threadIdx.x; sb < nsb; sb += 256) acc += a.partial[pidx(slot, a.nsys, sys, nb, sb)];
-        red[slot][threadIdx.x] = acc;
-    }
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int slot = 0; slot < 6; ++slot) red[slot][threadIdx.x] += red[slot][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
-    double P[6];
-    for (int slot = 0; slot < 6; ++slot) P[slot] = red[slot][0];
-    SysState &s = a.st[sys];
     switch (a.step) {
     case SC_ALPHA: {
         double den = P[0] * P[0] + P[1] * P[1];
         if (!(den > 0) || !finite_d(den)) {
             s.flags |= ST_BREAK;
-            a.active[sys] = 0;
+            act = 0;
             break;
         }
         // alpha = rho / r0v
@@ -254,7 +227,7 @@ __global__ __launch_bounds__(256) void k_scal(ScalArgs a)
             s.omega[0] = s.omega[1] = 0;
         } else {
             s.flags |= ST_BREAK;
-            a.active[sys] = 0;
+            act = 0;
         }
         break;
     }
@@ -264,7 +237,7 @@ __global__ __launch_bounds__(256) void k_scal(ScalArgs a)
         s.iter += 1;
         if (!finite_d(rr) || !finite_d(rho_n[0]) || !finite_d(rho_n[1])) {
             s.flags |= ST_BREAK;
-            a.active[sys] = 0;
+            act = 0;
             break;
         }
         s.rr = rr;
@@ -272,16 +245,16 @@ __global__ __launch_bounds__(256) void k_scal(ScalArgs a)
         if (rr < s.delta2 * s.rmax2) s.flags |= ST_WANT_UPD;
         if (rr <= s.stop2) {
             s.flags |= ST_CONV_ITER;
-            a.active[sys] = 0;
+            act = 0;
         } else if (s.iter >= s.max_iter) {
             s.flags |= ST_MAXIT;
-            a.active[sys] = 0;
+            act = 0;
         }
         double om2 = s.omega[0] * s.omega[0] + s.omega[1] * s.omega[1];
         double rh2 = s.rho[0] * s.rho[0] + s.rho[1] * s.rho[1];
-        if (a.active[sys] && (!(om2 > 0) || !(rh2 > 0))) {
+        if (act && (!(om2 > 0) || !(rh2 > 0))) {
             s.flags |= ST_BREAK;
-            a.active[sys] = 0;
+            act = 0;
         }
         if (om2 > 0 && rh2 > 0) {
             // beta = (rho_n / rho) * (alpha / omega)
@@ -315,9 +288,9 @@ __global__ __launch_bounds__(256) void k_scal(ScalArgs a)
         s.beta[0] = s.beta[1] = 0;
         if (P[5] <= s.stop2) {
             s.flags |= ST_CONV_ITER;
-            a.active[sys] = 0;
+            act = 0;
         } else {
-            a.active[sys] = 1;
+            act = 1;
         }
         break;
     case SC_CG_INIT:  // slot 2: |z|^2 with z = Dhat^+ r; slot 5: |r|^2
@@ -327,15 +300,15 @@ __global__ __launch_bounds__(256) void k_scal(ScalArgs a)
         s.flags &= ST_MAXIT;
         if (P[5] <= s.stop2 || !(P[2] > 0)) {
             s.flags |= ST_CONV_ITER;
-            a.active[sys] = 0;
+            act = 0;
         } else {
-            a.active[sys] = 1;
+            act = 1;
         }
         break;
     case SC_CG_ALPHA:  // slot 2: |q|^2 with q = Dhat p
         if (!(P[2] > 0) || !finite_d(P[2])) {
             s.flags |= ST_BREAK;
-            a.active[sys] = 0;
+            act = 0;
         } else {
             s.alpha[0] = s.zz / P[2];
         }
@@ -346,17 +319,17 @@ __global__ __launch_bounds__(256) void k_scal(ScalArgs a)
         s.rr = rr;
         if (!finite_d(zn) || !finite_d(rr)) {
             s.flags |= ST_BREAK;
-            a.active[sys] = 0;
+            act = 0;
             break;
         }
         s.beta[0] = zn / s.zz;
         s.zz = zn;
         if (rr <= s.stop2) {
             s.flags |= ST_CONV_ITER;
-            a.active[sys] = 0;
+            act = 0;
         } else if (s.iter >= s.max_iter) {
             s.flags |= ST_MAXIT;
-            a.active[sys] = 0;
+            act = 0;
         }
         break;
     }
@@ -364,16 +337,63 @@ __global__ __launch_bounds__(256) void k_scal(ScalArgs a)
     }
 }
 
+__global__ __launch_bounds__(256) void k_scal(ScalArgs a)
+{
+    const int sys = blockIdx.x;
+    if (a.mask) {
+        if (!a.mask[sys]) return;
+    } else if (!a.active[sys]) {
+        return;
+    }
+    int l = 0;
+    for (int k = 1; k < FL_MAXLAT; ++k)
+        if (k < a.B.nlat && sys >= a.B.lat[k].sys0) l = k;
+    const int nsb = a.B.lat[l].nsb, nb = a.B.nsb_max;
+    __shared__ double red[6][256];
+    __shared__ SysState snew;
+    for (int slot = 0; slot < 6; ++slot) {
+        double acc = 0;
+        for (int sb = threadIdx.x; sb < nsb; sb += 256) acc += a.partial[pidx(slot, a.nsys, sys, nb, sb)];
+        red[slot][threadIdx.x] = acc;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int slot = 0; slot < 6; ++slot) red[slot][threadIdx.x] += red[slot][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x >= FL_WAVE) return;
+    if (threadIdx.x == 0) {
+        double P[6];
+        for (int slot = 0; slot < 6; ++slot) P[slot] = red[slot][0];
+        SysState s = a.st[sys];
+        const int act0 = a.active[sys];
+        int act = act0;
+        scal_step(a, P, s, act);
+        snew = s;
+        if (act != act0) a.active[sys] = act;
+    }
+    // the flag store completes before the state is written as one store
+    // instruction of 8-byte words, one per lane, which ends the kernel
+    store_drain();
+    constexpr int NW = (int)(sizeof(SysState) / 8);
+    static_assert(sizeof(SysState) % 8 == 0, "SysState is written in 8-byte words");
+    if ((int)threadIdx.x < NW)
+        ((unsigned long long *)(a.st + sys))[threadIdx.x] = ((const unsigned long long *)&snew)[threadIdx.x];
+}
+
 }  // namespace
 
-void launch_blas(bool fp64, const BlasArgs &a, hipStream_t s)
+void launch_blas(VecFormat vf, const BlasArgs &a, hipStream_t s)
 {
     if (a.B.ntiles == 0) return;
     dim3 grid(a.B.ntiles), block(FL_WAVE * a.B.RT);
-    if (fp64)
+    if (vf == VEC_F64)
         dispatch<double>(a, grid, block, s);
-    else
+    else if (vf == VEC_F32)
         dispatch<float>(a, grid, block, s);
+    else
+        dispatch<H16>(a, grid, block, s);
 }
 
 void launch_scalars(const ScalArgs &a, hipStream_t s)

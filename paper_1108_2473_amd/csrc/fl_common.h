@@ -98,6 +98,8 @@ __device__ __forceinline__ cx<R> cmsub(cx<R> acc, cx<R> a, cx<R> b)
 // ---------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
 
 struct Buf {
     __amdgpu_buffer_rsrc_t r;
@@ -123,6 +125,60 @@ __device__ __forceinline__ v2f buf_ld8(const Buf &b, int voff, int soff)
 __device__ __forceinline__ void buf_st16(const Buf &b, v4f v, int voff, int soff)
 {
     __builtin_amdgcn_raw_buffer_store_b128(v, b.r, voff, soff, 0);
+}
+
+// Store groups.  Measured on gfx950: a vector instruction issued shortly
+// after a vector-memory store can overwrite the store's data registers
+// before the store has read them when the memory pipeline is congested (the
+// compiler's hazard model does not cover stores with a scalar offset
+// register), which corrupts the stored data.  Every group of stores in this
+// library is therefore issued back to back from registers prepared before
+// it, with no vector instruction in between (scalar component offsets and
+// one lane offset, or precomputed addresses), and followed by store_drain()
+// before any further vector work; a store that ends a kernel needs no drain.
+__device__ __forceinline__ void store_drain()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), gfx9 encoding
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ void store_fence_begin() { __builtin_amdgcn_sched_barrier(0); }
+
+__device__ __forceinline__ void buf_st8(const Buf &b, v2f v, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(v, b.r, voff, soff, 0);
+}
+
+// N 16-byte vectors of one lane at byte offsets voff + c * cstride (cstride
+// wave-uniform), as one store group
+template <int N>
+__device__ __forceinline__ void st16_group(const Buf &b, const v4f (&v)[N], int voff, int cstride)
+{
+    store_fence_begin();
+#pragma unroll
+    for (int c = 0; c < N; ++c) buf_st16(b, v[c], voff, c * cstride);
+    store_drain();
+}
+
+// N values through precomputed addresses, as one store group
+template <int N, typename T>
+__device__ __forceinline__ void ptr_store_group(T *const (&p)[N], const T (&v)[N])
+{
+    store_fence_begin();
+#pragma unroll
+    for (int c = 0; c < N; ++c) *p[c] = v[c];
+    store_drain();
+}
+
+__device__ __forceinline__ float buf_ld4(const Buf &b, int voff, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void buf_st4(const Buf &b, float v, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, voff, soff, 0);
 }
 
 __device__ __forceinline__ double2 v4f_to_d2(v4f v)
@@ -151,10 +207,22 @@ __device__ __forceinline__ v4f d2_to_v4f(double2 d)
 template <typename R>
 struct SpinorFmt;
 
+//
+// Every format provides, for the component-major layout of one right-hand
+// side's field on Vh sites (SITE_BYTES per site):
+//   load/store    through a per-wave buffer view (and plain pointers for
+//                 FP64/FP32),
+//   load_raw      the values up to one common per-site factor, returned
+//                 (1 for FP64/FP32) so that a stencil can fold it into the
+//                 scalar it multiplies the hop by,
+//   to_lds/lds_load_raw  the raw site copied into, and read back from, a
+//                 wave's LDS window of wsmax sites.
 template <>
 struct SpinorFmt<double> {
+    typedef double R;
     typedef double2 V;
     static constexpr int NC = 12;
+    static constexpr int SITE_BYTES = 192;
     __device__ static __forceinline__ void load(const V *__restrict__ f, int Vh, int i, cx<double> s[12])
     {
 #pragma unroll
@@ -165,8 +233,14 @@ struct SpinorFmt<double> {
     }
     __device__ static __forceinline__ void store(V *__restrict__ f, int Vh, int i, const cx<double> s[12])
     {
+        V *p[12];
+        V v[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) f[(size_t)c * Vh + i] = make_double2(s[c].re, s[c].im);
+        for (int c = 0; c < 12; ++c) {
+            p[c] = f + (size_t)c * Vh + i;
+            v[c] = make_double2(s[c].re, s[c].im);
+        }
+        ptr_store_group(p, v);
     }
     // buffer views of one right-hand side's field (component stride Vh*16 bytes)
     __device__ static __forceinline__ void load(const Buf &b, int Vh, int i, cx<double> s[12])
@@ -179,15 +253,38 @@ struct SpinorFmt<double> {
     }
     __device__ static __forceinline__ void store(const Buf &b, int Vh, int i, const cx<double> s[12])
     {
+        v4f v[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) buf_st16(b, d2_to_v4f(make_double2(s[c].re, s[c].im)), i * 16, c * Vh * 16);
+        for (int c = 0; c < 12; ++c) v[c] = d2_to_v4f(make_double2(s[c].re, s[c].im));
+        st16_group(b, v, i * 16, Vh * 16);
+    }
+    __device__ static __forceinline__ double load_raw(const Buf &b, int Vh, int i, cx<double> s[12])
+    {
+        load(b, Vh, i, s);
+        return 1.0;
+    }
+    __device__ static __forceinline__ void to_lds(const Buf &b, int Vh, int i, unsigned char *w, int wsmax, int j)
+    {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) ((v4f *)w)[c * wsmax + j] = buf_ld16(b, i * 16, c * Vh * 16);
+    }
+    __device__ static __forceinline__ double lds_load_raw(const unsigned char *w, int wsmax, int j, cx<double> s[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            double2 v = v4f_to_d2(((const v4f *)w)[c * wsmax + j]);
+            s[c] = cx<double>{v.x, v.y};
+        }
+        return 1.0;
     }
 };
 
 template <>
 struct SpinorFmt<float> {
+    typedef float R;
     typedef float4 V;
     static constexpr int NC = 6;
+    static constexpr int SITE_BYTES = 96;
     __device__ static __forceinline__ void load(const V *__restrict__ f, int Vh, int i, cx<float> s[12])
     {
 #pragma unroll
@@ -199,9 +296,14 @@ struct SpinorFmt<float> {
     }
     __device__ static __forceinline__ void store(V *__restrict__ f, int Vh, int i, const cx<float> s[12])
     {
+        V *p[6];
+        V v[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c)
-            f[(size_t)c * Vh + i] = make_float4(s[2 * c].re, s[2 * c].im, s[2 * c + 1].re, s[2 * c + 1].im);
+        for (int c = 0; c < 6; ++c) {
+            p[c] = f + (size_t)c * Vh + i;
+            v[c] = make_float4(s[2 * c].re, s[2 * c].im, s[2 * c + 1].re, s[2 * c + 1].im);
+        }
+        ptr_store_group(p, v);
     }
     __device__ static __forceinline__ void load(const Buf &b, int Vh, int i, cx<float> s[12])
     {
@@ -214,13 +316,141 @@ struct SpinorFmt<float> {
     }
     __device__ static __forceinline__ void store(const Buf &b, int Vh, int i, const cx<float> s[12])
     {
+        v4f v[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = v4f{s[2 * c].re, s[2 * c].im, s[2 * c + 1].re, s[2 * c + 1].im};
+        st16_group(b, v, i * 16, Vh * 16);
+    }
+    __device__ static __forceinline__ float load_raw(const Buf &b, int Vh, int i, cx<float> s[12])
+    {
+        load(b, Vh, i, s);
+        return 1.0f;
+    }
+    __device__ static __forceinline__ void to_lds(const Buf &b, int Vh, int i, unsigned char *w, int wsmax, int j)
+    {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ((v4f *)w)[c * wsmax + j] = buf_ld16(b, i * 16, c * Vh * 16);
+    }
+    __device__ static __forceinline__ float lds_load_raw(const unsigned char *w, int wsmax, int j, cx<float> s[12])
+    {
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            v4f v = {s[2 * c].re, s[2 * c].im, s[2 * c + 1].re, s[2 * c + 1].im};
-            buf_st16(b, v, i * 16, c * Vh * 16);
+            v4f v = ((const v4f *)w)[c * wsmax + j];
+            s[2 * c] = cx<float>{v.x, v.y};
+            s[2 * c + 1] = cx<float>{v.z, v.w};
         }
+        return 1.0f;
     }
 };
+
+// 16-bit fixed-point spinor storage with one FP32 scale per site: the 24
+// reals of a site are divided by their largest magnitude m and stored as
+// round(32767 v / m) in int16 (three 16-byte vectors, complex entry 4c + w in
+// word w of vector c, real part in the low half); the scale m / 32767 follows
+// the three vector arrays as an FP32 array.  Relative rounding error per
+// component <= 1 / 65534 of the site's largest component.
+struct H16 {};
+
+__device__ __forceinline__ cx<float> h16_pair(unsigned w)
+{
+    return cx<float>{(float)(int)(short)(w & 0xffffu), (float)((int)w >> 16)};
+}
+
+
+__device__ __forceinline__ unsigned h16_pack(float a, float b)
+{
+    // a, b in [-1, 1] (clamped) -> round(32767 a) | round(32767 b) << 16
+    return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pknorm_i16(a, b));
+}
+
+template <>
+struct SpinorFmt<H16> {
+    typedef float R;
+    static constexpr int NC = 3;
+    static constexpr int SITE_BYTES = 52;
+    __device__ static __forceinline__ void unpack(const v4f v[3], cx<float> s[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            // reinterpret the whole vector: a bit cast of one element
+            // accessor (v[c].y) reads the bytes of element 0
+            const v4u u = __builtin_bit_cast(v4u, v[c]);
+            s[4 * c] = h16_pair(u.x);
+            s[4 * c + 1] = h16_pair(u.y);
+            s[4 * c + 2] = h16_pair(u.z);
+            s[4 * c + 3] = h16_pair(u.w);
+        }
+    }
+    __device__ static __forceinline__ float load_raw(const Buf &b, int Vh, int i, cx<float> s[12])
+    {
+        v4f v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = buf_ld16(b, i * 16, c * Vh * 16);
+        const float sc = buf_ld4(b, i * 4, 3 * Vh * 16);
+        unpack(v, s);
+        return sc;
+    }
+    __device__ static __forceinline__ void load(const Buf &b, int Vh, int i, cx<float> s[12])
+    {
+        const float sc = load_raw(b, Vh, i, s);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) s[k] = cx<float>{s[k].re * sc, s[k].im * sc};
+    }
+    // stores s and replaces it by the stored (rounded) values
+    __device__ static __forceinline__ void store(const Buf &b, int Vh, int i, cx<float> s[12])
+    {
+        float m = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s[k].re), fabsf(s[k].im)));
+        const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+        const float sc = m * (1.0f / 32767.0f);
+        unsigned w[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            w[k] = h16_pack(s[k].re * inv, s[k].im * inv);
+            cx<float> q = h16_pair(w[k]);
+            s[k] = cx<float>{q.re * sc, q.im * sc};
+        }
+        v4f v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const v4u u = {w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]};
+            v[c] = __builtin_bit_cast(v4f, u);
+        }
+        // both lane offsets exist before the group, so no vector instruction
+        // runs between its stores
+        int vo16 = i * 16, vo4 = i * 4;
+        float scv = sc;
+        asm volatile("" : "+v"(vo16), "+v"(vo4), "+v"(scv));
+        store_fence_begin();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) buf_st16(b, v[c], vo16, c * Vh * 16);
+        buf_st4(b, scv, vo4, 3 * Vh * 16);
+        store_drain();
+    }
+    __device__ static __forceinline__ void to_lds(const Buf &b, int Vh, int i, unsigned char *w, int wsmax, int j)
+    {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ((v4f *)w)[c * wsmax + j] = buf_ld16(b, i * 16, c * Vh * 16);
+        ((float *)(w + (size_t)3 * 16 * wsmax))[j] = buf_ld4(b, i * 4, 3 * Vh * 16);
+    }
+    __device__ static __forceinline__ float lds_load_raw(const unsigned char *w, int wsmax, int j, cx<float> s[12])
+    {
+        v4f v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = ((const v4f *)w)[c * wsmax + j];
+        unpack(v, s);
+        return ((const float *)(w + (size_t)3 * 16 * wsmax))[j];
+    }
+};
+
+// per-wave buffer view of right-hand side `rhs` of a field in format S
+template <typename S>
+__device__ __forceinline__ Buf spinor_buf(const void *base, int Vh, int rhs)
+{
+    const size_t per = (size_t)SpinorFmt<S>::SITE_BYTES * (size_t)Vh;
+    return make_buf((const unsigned char *)base + (size_t)rhs * per, (unsigned)per);
+}
 
 // ---------------------------------------------------------------------------
 // bfloat16: round-to-nearest-even from fp32 (the top 16 bits of the fp32
@@ -351,6 +581,35 @@ struct LinkBF16R12 {
         } cv;
         cv.f = f;
         return cv.u;
+    }
+};
+
+// 16-bit fixed point, rows 0 and 1: every entry of an SU(3) matrix has
+// |re|, |im| <= 1, so each real is stored as round(32767 u) (absolute error
+// <= 1/65534), four per 8-byte vector
+struct LinkQ16R12 {
+    typedef float R;
+    typedef uint2 V;
+    static constexpr int NC = 3;
+    static constexpr int REALS = 12;
+    static constexpr int BYTES = 24;
+    static constexpr int ESZ = 8;
+    __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
+    {
+        constexpr float q = 1.0f / 32767.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            int e = 2 * c;
+            cx<float> a = h16_pair(v[c].x), b = h16_pair(v[c].y);
+            U[e / 3][e % 3] = cx<float>{a.re * q, a.im * q};
+            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{b.re * q, b.im * q};
+        }
+        rebuild_row2(U);
+    }
+    __device__ static __forceinline__ V buf_get(const Buf &g, int voff, int soff)
+    {
+        const v2u u = __builtin_bit_cast(v2u, buf_ld8(g, voff, soff));
+        return make_uint2(u.x, u.y);
     }
 };
 
@@ -489,4 +748,15 @@ __device__ __forceinline__ double wave_sum(double v)
 __device__ __forceinline__ size_t pidx(int slot, int nsys, int sys, int nsb_max, int sb)
 {
     return ((size_t)slot * nsys + sys) * nsb_max + sb;
+}
+
+// A wave's sums s0, s1, s2 (equal in every lane) as a single store
+// instruction at the end of a kernel: lane k < 3 writes slot slot0 + k when
+// bit k of `which` is set.
+__device__ __forceinline__ void write_partials(double *partial, int slot0, int nsys, int sys, int nsb_max, int sb,
+                                               double s0, double s1, double s2, int which)
+{
+    const int lane = threadIdx.x % FL_WAVE;
+    const double v = lane == 0 ? s0 : (lane == 1 ? s1 : s2);
+    if (lane < 3 && ((which >> lane) & 1)) partial[pidx(slot0 + lane, nsys, sys, nsb_max, sb)] = v;
 }

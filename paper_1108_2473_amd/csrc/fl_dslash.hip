@@ -25,18 +25,17 @@
 
 namespace {
 
-template <typename R, int EPI>
+// S: storage format of the fields (SpinorFmt<S>), arithmetic in SpinorFmt<S>::R.
+// The reductions use the values as stored (after any rounding of the format).
+template <typename S, int EPI, typename R>
 __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T, const LatGeom &g, int rhs,
                                          const cx<R> acc[12], R &q0, R &q1, R &q2)
 {
-    typedef typename SpinorFmt<R>::V SV;
-    const size_t fs = (size_t)SpinorFmt<R>::NC * g.Vh;
-    const unsigned fbytes = (unsigned)(fs * sizeof(SV));
+    typedef SpinorFmt<S> F;
     const R cb = (R)a.cb[T.lat];
-    cx<R> out[12];
+    cx<R> out[12], xv[12];
     if (EPI & EPI_XPAY) {
-        cx<R> xv[12];
-        SpinorFmt<R>::load(make_buf((const SV *)a.x[T.lat] + rhs * fs, fbytes), g.Vh, T.site, xv);
+        F::load(spinor_buf<S>(a.x[T.lat], g.Vh, rhs), g.Vh, T.site, xv);
         const R ca = (R)a.ca[T.lat];
         if (ca == (R)1) {
 #pragma unroll
@@ -45,23 +44,23 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
 #pragma unroll
             for (int k = 0; k < 12; ++k) out[k] = ca * xv[k] + cb * acc[k];
         }
-        if (EPI & EPI_DOTX_NORM) {
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                cx<R> d = cjmul(out[k], xv[k]);
-                q0 += d.re;
-                q1 += d.im;
-                q2 += out[k].re * out[k].re + out[k].im * out[k].im;
-            }
-        }
     } else {
 #pragma unroll
         for (int k = 0; k < 12; ++k) out[k] = cb * acc[k];
     }
-    SpinorFmt<R>::store(make_buf((SV *)a.out[T.lat] + rhs * fs, fbytes), g.Vh, T.site, out);
+    F::store(spinor_buf<S>(a.out[T.lat], g.Vh, rhs), g.Vh, T.site, out);
+    if (EPI & EPI_DOTX_NORM) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            cx<R> d = cjmul(out[k], xv[k]);
+            q0 += d.re;
+            q1 += d.im;
+            q2 += out[k].re * out[k].re + out[k].im * out[k].im;
+        }
+    }
     if (EPI & EPI_DOTY) {
         cx<R> yv[12];
-        SpinorFmt<R>::load(make_buf((const SV *)a.y[T.lat] + rhs * fs, fbytes), g.Vh, T.site, yv);
+        F::load(spinor_buf<S>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, yv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             cx<R> d = cjmul(yv[k], out[k]);
@@ -80,56 +79,48 @@ __device__ __forceinline__ void reduce_partials(const DslashArgs &a, const TileI
 {
     if (EPI & (EPI_DOTY | EPI_DOTX_NORM | EPI_NORM)) {
         double s0 = wave_sum((double)q0), s1 = wave_sum((double)q1), s2 = wave_sum((double)q2);
-        if (threadIdx.x % FL_WAVE == 0) {
-            const int ns = a.nsys, nb = a.B.nsb_max;
-            if (EPI & (EPI_DOTY | EPI_DOTX_NORM)) {
-                a.partial[pidx(a.slot0, ns, T.sys, nb, T.sb)] = s0;
-                a.partial[pidx(a.slot0 + 1, ns, T.sys, nb, T.sb)] = s1;
-            }
-            if (EPI & (EPI_DOTX_NORM | EPI_NORM)) a.partial[pidx(a.slot0 + 2, ns, T.sys, nb, T.sb)] = s2;
-        }
+        constexpr int which = ((EPI & (EPI_DOTY | EPI_DOTX_NORM)) ? 3 : 0) | ((EPI & (EPI_DOTX_NORM | EPI_NORM)) ? 4 : 0);
+        write_partials(a.partial, a.slot0, a.nsys, T.sys, a.B.nsb_max, T.sb, s0, s1, s2, which);
     }
 }
 
-template <typename R, class LK, bool DAG, int EPI>
-__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_dslash(DslashArgs a)
+template <typename S, class LK, bool DAG, int EPI>
+__global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024) void k_dslash(DslashArgs a)
 {
-    typedef typename SpinorFmt<R>::V SV;
+    typedef typename SpinorFmt<S>::R R;
     TileInfo T = tile_info(a.B);
     if (!T.valid_rhs) return;
     if (a.mask && !a.mask[T.sys]) return;  // wave-uniform: one wave = one right-hand side
     const LatGeom &g = a.B.lat[T.lat];
     const int rhs = __builtin_amdgcn_readfirstlane(T.rhs);
-    const size_t fs = (size_t)SpinorFmt<R>::NC * g.Vh;
-    const unsigned fbytes = (unsigned)(fs * sizeof(SV));
     R q0 = 0, q1 = 0, q2 = 0;
     if (T.valid_site) {
         Coord c = cb_coords(g, a.par, T.site);
-        BufSrc<R, LK> src;
-        src.in = make_buf((const SV *)a.in[T.lat] + rhs * fs, fbytes);
+        BufSrc<S, LK> src;
+        src.in = spinor_buf<S>(a.in[T.lat], g.Vh, rhs);
         src.gauge = make_buf(a.gauge[T.lat], (unsigned)(8u * LK::NC * LK::ESZ * (unsigned)g.Vh));
         src.Vh = g.Vh;
         cx<R> acc[12];
         hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
-        epilogue<R, EPI>(a, T, g, rhs, acc, q0, q1, q2);
+        epilogue<S, EPI>(a, T, g, rhs, acc, q0, q1, q2);
     }
     reduce_partials<EPI>(a, T, q0, q1, q2);
 }
 
-template <typename R, class LK, bool SLINK>
+template <typename S, class LK, bool SLINK>
 struct LdsSrc {
-    typedef typename SpinorFmt<R>::V SV;
+    typedef typename SpinorFmt<S>::R R;
     Buf in, gauge;
     int Vh, wlo, wsz, wsmax, p, lane;
-    const SV *win;
+    const unsigned char *win;
     const typename LK::V *lk;
     template <int MU>
-    __device__ __forceinline__ void spinor(int i, cx<R> s[12]) const
+    __device__ __forceinline__ R spinor(int i, cx<R> s[12]) const
     {
         if (MU < 2)
-            SpinorFmt<R>::load(win, wsmax, i - wlo, s);
+            return SpinorFmt<S>::lds_load_raw(win, wsmax, i - wlo, s);
         else
-            SpinorFmt<R>::load(in, Vh, i, s);
+            return SpinorFmt<S>::load_raw(in, Vh, i, s);
     }
     __device__ __forceinline__ void link(int mu, int par, int i, cx<R> U[3][3]) const
     {
@@ -163,12 +154,12 @@ __device__ __forceinline__ int back_neighbour(const LatGeom &g, const Coord &c, 
     return xh + Lh0 * (c.y + Ly * (c.z + Lz * tb));
 }
 
-template <typename R, class LK, bool DAG, int EPI, bool SLINK>
-__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_dslash_lds(DslashArgs a)
+template <typename S, class LK, bool DAG, int EPI, bool SLINK>
+__global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024) void k_dslash_lds(DslashArgs a)
 {
-    typedef typename SpinorFmt<R>::V SV;
+    typedef typename SpinorFmt<S>::R R;
     typedef typename LK::V LV;
-    constexpr int NCS = SpinorFmt<R>::NC;
+    constexpr int SB = SpinorFmt<S>::SITE_BYTES;
     extern __shared__ unsigned char smem[];
     TileInfo T = tile_info(a.B);
     const LatGeom &g = a.B.lat[T.lat];
@@ -180,14 +171,13 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_dslash_lds(Dsla
     const int wlo = (i0 / plane) * plane;
     const int wsz = min(Vh, (min(i0 + FL_WAVE, Vh) - 1) / plane * plane + plane) - wlo;
     const int wsmax = a.wsmax;
-    SV *win = (SV *)smem + (size_t)wave * NCS * wsmax;
-    LV *lk = (LV *)((SV *)smem + (size_t)a.B.RT * NCS * wsmax);
+    // wsmax is a multiple of 4, so that every window starts 16-byte aligned
+    unsigned char *win = smem + (size_t)wave * SB * wsmax;
+    LV *lk = (LV *)(smem + (size_t)a.B.RT * SB * wsmax);
     const bool live = T.valid_rhs && !(a.mask && !a.mask[T.sys]);
     const int rhs = __builtin_amdgcn_readfirstlane(T.valid_rhs ? T.rhs : 0);
-    const size_t fs = (size_t)NCS * Vh;
-    const unsigned fbytes = (unsigned)(fs * sizeof(SV));
     const Buf gbuf = make_buf(a.gauge[T.lat], (unsigned)(8u * LK::NC * LK::ESZ * (unsigned)Vh));
-    Buf ibuf = make_buf((const SV *)a.in[T.lat] + rhs * fs, fbytes);
+    Buf ibuf = spinor_buf<S>(a.in[T.lat], Vh, rhs);
     if (SLINK) {
         // the 8 links (4 forward at the site, 4 backward at the neighbour) of
         // the block's 64 sites, shared by all its right-hand sides
@@ -213,22 +203,14 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_dslash_lds(Dsla
             for (int cc = 0; cc < LK::NC; ++cc) lk[(dslot * LK::NC + cc) * FL_WAVE + s] = v[cc];
         }
     }
-    if (live) {
-        for (int j = lane; j < wsz; j += FL_WAVE)
-#pragma unroll
-            for (int c = 0; c < NCS; ++c) {
-                v4f v = buf_ld16(ibuf, (wlo + j) * 16, c * Vh * 16);
-                SV o;
-                __builtin_memcpy(&o, &v, 16);
-                win[c * wsmax + j] = o;
-            }
-    }
+    if (live)
+        for (int j = lane; j < wsz; j += FL_WAVE) SpinorFmt<S>::to_lds(ibuf, Vh, wlo + j, win, wsmax, j);
     __syncthreads();
     if (!live) return;
     R q0 = 0, q1 = 0, q2 = 0;
     if (T.valid_site) {
         Coord c = cb_coords(g, a.par, T.site);
-        LdsSrc<R, LK, SLINK> src;
+        LdsSrc<S, LK, SLINK> src;
         src.in = ibuf;
         src.gauge = gbuf;
         src.Vh = Vh;
@@ -241,54 +223,54 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 1024) void k_dslash_lds(Dsla
         src.lk = lk;
         cx<R> acc[12];
         hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
-        epilogue<R, EPI>(a, T, g, rhs, acc, q0, q1, q2);
+        epilogue<S, EPI>(a, T, g, rhs, acc, q0, q1, q2);
     }
     reduce_partials<EPI>(a, T, q0, q1, q2);
 }
 
-template <typename R, class LK>
+template <typename S, class LK>
 size_t dslash_lds_bytes_t(int RT, int wsmax, int lds)
 {
-    size_t b = (size_t)RT * SpinorFmt<R>::NC * wsmax * 16;
+    size_t b = (size_t)RT * SpinorFmt<S>::SITE_BYTES * wsmax;
     if (lds == 2) b += (size_t)8 * LK::NC * FL_WAVE * sizeof(typename LK::V);
     return b;
 }
 
-template <typename R, class LK, bool DAG, int EPI>
+template <typename S, class LK, bool DAG, int EPI>
 void launch_one(const DslashArgs &a, dim3 grid, dim3 block, hipStream_t s)
 {
     if (a.lds == 0) {
-        hipLaunchKernelGGL((k_dslash<R, LK, DAG, EPI>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_dslash<S, LK, DAG, EPI>), grid, block, 0, s, a);
     } else {
-        size_t shm = dslash_lds_bytes_t<R, LK>(a.B.RT, a.wsmax, a.lds);
+        size_t shm = dslash_lds_bytes_t<S, LK>(a.B.RT, a.wsmax, a.lds);
         if (a.lds == 2)
-            hipLaunchKernelGGL((k_dslash_lds<R, LK, DAG, EPI, true>), grid, block, shm, s, a);
+            hipLaunchKernelGGL((k_dslash_lds<S, LK, DAG, EPI, true>), grid, block, shm, s, a);
         else
-            hipLaunchKernelGGL((k_dslash_lds<R, LK, DAG, EPI, false>), grid, block, shm, s, a);
+            hipLaunchKernelGGL((k_dslash_lds<S, LK, DAG, EPI, false>), grid, block, shm, s, a);
     }
 }
 
-template <typename R, class LK, bool DAG>
+template <typename S, class LK, bool DAG>
 void dispatch_epi(const DslashArgs &a, int epi, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (epi) {
-    case EPI_PLAIN: launch_one<R, LK, DAG, EPI_PLAIN>(a, grid, block, s); break;
-    case EPI_XPAY: launch_one<R, LK, DAG, EPI_XPAY>(a, grid, block, s); break;
-    case EPI_XPAY | EPI_NORM: launch_one<R, LK, DAG, EPI_XPAY | EPI_NORM>(a, grid, block, s); break;
-    case EPI_XPAY | EPI_DOTY: launch_one<R, LK, DAG, EPI_XPAY | EPI_DOTY>(a, grid, block, s); break;
-    case EPI_XPAY | EPI_DOTX_NORM: launch_one<R, LK, DAG, EPI_XPAY | EPI_DOTX_NORM>(a, grid, block, s); break;
-    case EPI_NORM: launch_one<R, LK, DAG, EPI_NORM>(a, grid, block, s); break;
+    case EPI_PLAIN: launch_one<S, LK, DAG, EPI_PLAIN>(a, grid, block, s); break;
+    case EPI_XPAY: launch_one<S, LK, DAG, EPI_XPAY>(a, grid, block, s); break;
+    case EPI_XPAY | EPI_NORM: launch_one<S, LK, DAG, EPI_XPAY | EPI_NORM>(a, grid, block, s); break;
+    case EPI_XPAY | EPI_DOTY: launch_one<S, LK, DAG, EPI_XPAY | EPI_DOTY>(a, grid, block, s); break;
+    case EPI_XPAY | EPI_DOTX_NORM: launch_one<S, LK, DAG, EPI_XPAY | EPI_DOTX_NORM>(a, grid, block, s); break;
+    case EPI_NORM: launch_one<S, LK, DAG, EPI_NORM>(a, grid, block, s); break;
     default: break;
     }
 }
 
-template <typename R, class LK>
+template <typename S, class LK>
 void dispatch_dag(const DslashArgs &a, bool dag, int epi, dim3 grid, dim3 block, hipStream_t s)
 {
     if (dag)
-        dispatch_epi<R, LK, true>(a, epi, grid, block, s);
+        dispatch_epi<S, LK, true>(a, epi, grid, block, s);
     else
-        dispatch_epi<R, LK, false>(a, epi, grid, block, s);
+        dispatch_epi<S, LK, false>(a, epi, grid, block, s);
 }
 
 }  // namespace
@@ -300,6 +282,7 @@ size_t dslash_lds_bytes(LinkFormat fmt, int RT, int wsmax, int lds)
     case LINK_F64_R18: return dslash_lds_bytes_t<double, LinkF64R18>(RT, wsmax, lds);
     case LINK_F32_R18: return dslash_lds_bytes_t<float, LinkF32R18>(RT, wsmax, lds);
     case LINK_F32_R12: return dslash_lds_bytes_t<float, LinkF32R12>(RT, wsmax, lds);
+    case LINK_Q16_R12: return dslash_lds_bytes_t<H16, LinkQ16R12>(RT, wsmax, lds);
     default: return dslash_lds_bytes_t<float, LinkBF16R12>(RT, wsmax, lds);
     }
 }
@@ -319,5 +302,7 @@ void launch_dslash(LinkFormat fmt, const DslashArgs &a, bool dag, int epi, hipSt
     case LINK_F32_R18: dispatch_dag<float, LinkF32R18>(a, dag, epi, grid, block, s); break;
     case LINK_F32_R12: dispatch_dag<float, LinkF32R12>(a, dag, epi, grid, block, s); break;
     case LINK_BF16_R12: dispatch_dag<float, LinkBF16R12>(a, dag, epi, grid, block, s); break;
+    case LINK_Q16_R12: dispatch_dag<H16, LinkQ16R12>(a, dag, epi, grid, block, s); break;
+    default: break;
     }
 }

@@ -42,8 +42,14 @@ __global__ void k_canon_to_eo(const double *__restrict__ canon, double2 *even, d
     LexSite ls = lex_site(g, s);
     double2 *f = (ls.par ? odd : even) + (size_t)rhs * 12 * g.Vh;
     const double *src = canon + (size_t)id * 24;
+    double2 *p[12];
+    double2 v[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) f[(size_t)c * g.Vh + ls.cb] = make_double2(src[2 * c], src[2 * c + 1]);
+    for (int c = 0; c < 12; ++c) {
+        p[c] = f + (size_t)c * g.Vh + ls.cb;
+        v[c] = make_double2(src[2 * c], src[2 * c + 1]);
+    }
+    ptr_store_group(p, v);
 }
 
 __global__ void k_eo_to_canon(const double2 *even, const double2 *odd, double *__restrict__ canon,
@@ -56,13 +62,15 @@ __global__ void k_eo_to_canon(const double2 *even, const double2 *odd, double *_
     long long s = id - (long long)rhs * V;
     LexSite ls = lex_site(g, s);
     const double2 *f = (ls.par ? odd : even) + (size_t)rhs * 12 * g.Vh;
-    double *dst = canon + (size_t)id * 24;
+    double2 *dst = (double2 *)(canon + (size_t)id * 24);
+    double2 *p[12];
+    double2 v[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        double2 v = f[(size_t)c * g.Vh + ls.cb];
-        dst[2 * c] = v.x;
-        dst[2 * c + 1] = v.y;
+        v[c] = f[(size_t)c * g.Vh + ls.cb];
+        p[c] = dst + c;
     }
+    ptr_store_group(p, v);
 }
 
 // --- links --------------------------------------------------------------
@@ -79,23 +87,59 @@ __global__ void k_pack_links(const double *__restrict__ canon, void *dst, int fm
     size_t base = (size_t)(mu * 2 + ls.par);
     if (fmt == LINK_F64_R18) {
         double2 *d = (double2 *)dst + base * 9 * Vh;
-        for (int c = 0; c < 9; ++c) d[c * Vh + ls.cb] = make_double2(u[2 * c], u[2 * c + 1]);
+        double2 *p[9];
+        double2 v[9];
+        for (int c = 0; c < 9; ++c) {
+            p[c] = d + c * Vh + ls.cb;
+            v[c] = make_double2(u[2 * c], u[2 * c + 1]);
+        }
+        ptr_store_group(p, v);
     } else if (fmt == LINK_F32_R18) {
         float2 *d = (float2 *)dst + base * 9 * Vh;
-        for (int c = 0; c < 9; ++c) d[c * Vh + ls.cb] = make_float2((float)u[2 * c], (float)u[2 * c + 1]);
+        float2 *p[9];
+        float2 v[9];
+        for (int c = 0; c < 9; ++c) {
+            p[c] = d + c * Vh + ls.cb;
+            v[c] = make_float2((float)u[2 * c], (float)u[2 * c + 1]);
+        }
+        ptr_store_group(p, v);
     } else if (fmt == LINK_F32_R12) {
         float4 *d = (float4 *)dst + base * 3 * Vh;
-        for (int c = 0; c < 3; ++c)
-            d[c * Vh + ls.cb] = make_float4((float)u[4 * c], (float)u[4 * c + 1], (float)u[4 * c + 2],
-                                            (float)u[4 * c + 3]);
+        float4 *p[3];
+        float4 v[3];
+        for (int c = 0; c < 3; ++c) {
+            p[c] = d + c * Vh + ls.cb;
+            v[c] = make_float4((float)u[4 * c], (float)u[4 * c + 1], (float)u[4 * c + 2], (float)u[4 * c + 3]);
+        }
+        ptr_store_group(p, v);
+    } else if (fmt == LINK_Q16_R12) {
+        // round(32767 u) of each real of rows 0 and 1 (|u| <= 1 for SU(3))
+        uint2 *d = (uint2 *)dst + base * 3 * Vh;
+        uint2 *p[3];
+        uint2 v[3];
+        for (int c = 0; c < 3; ++c) {
+            uint32_t q[4];
+            for (int k = 0; k < 4; ++k) {
+                double x = rint(32767.0 * u[4 * c + k]);
+                x = x > 32767.0 ? 32767.0 : (x < -32767.0 ? -32767.0 : x);
+                q[k] = (uint32_t)(uint16_t)(int16_t)(int)x;
+            }
+            p[c] = d + c * Vh + ls.cb;
+            v[c] = make_uint2(q[0] | (q[1] << 16), q[2] | (q[3] << 16));
+        }
+        ptr_store_group(p, v);
     } else {
         uint2 *d = (uint2 *)dst + base * 3 * Vh;
+        uint2 *p[3];
+        uint2 v[3];
         for (int c = 0; c < 3; ++c) {
             // fp64 -> fp32 (nearest) -> bf16 (nearest even)
             uint32_t h0 = f32_to_bf16_rne((float)u[4 * c]), h1 = f32_to_bf16_rne((float)u[4 * c + 1]);
             uint32_t h2 = f32_to_bf16_rne((float)u[4 * c + 2]), h3 = f32_to_bf16_rne((float)u[4 * c + 3]);
-            d[c * Vh + ls.cb] = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+            p[c] = d + c * Vh + ls.cb;
+            v[c] = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
         }
+        ptr_store_group(p, v);
     }
 }
 
@@ -197,15 +241,21 @@ __global__ void k_noise_sources(double2 *even, double2 *odd, NoiseBatch nb, LatG
     const int *job = nb.job + JOB_INTS * j;
     const uint64_t r = (uint64_t)(uint32_t)job[JOB_R];
     double2 *f = (ls.par ? odd : even) + (size_t)j * 12 * g.Vh;
+    double2 *p[12];
+    double2 v[12];
+#pragma unroll
     for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double2 v = make_double2(0.0, 0.0);
+            double2 x = make_double2(0.0, 0.0);
             if (in_support(nb.dil, job, ls, sp, a)) {
                 uint64_t key = ((r * (uint64_t)V + (uint64_t)s) * 4 + (uint64_t)sp) * 3 + (uint64_t)a;
-                v = noise_value(nb.type, splitmix_output(nb.seed, key));
+                x = noise_value(nb.type, splitmix_output(nb.seed, key));
             }
-            f[(size_t)(3 * sp + a) * g.Vh + ls.cb] = v;
+            v[3 * sp + a] = x;
+            p[3 * sp + a] = f + (size_t)(3 * sp + a) * g.Vh + ls.cb;
         }
+    ptr_store_group(p, v);
 }
 
 // --- contractions ---------------------------------------------------------
@@ -251,11 +301,17 @@ __global__ void k_exact_contract(ExactContractArgs a)
                 acc = acc + gba * S[al][be];
             }
         a.L[gi * a.L_stride + a.L_off + k] = make_double2(acc.re, acc.im);
+        store_drain();  // one store per gamma (their number is a run-time value)
     }
     if (a.S) {
-        double2 *o = a.S + (a.L_off + k) * 16;
+        double2 *p[16];
+        double2 v[16];
         for (int al = 0; al < 4; ++al)
-            for (int be = 0; be < 4; ++be) o[4 * al + be] = make_double2(S[al][be].re, S[al][be].im);
+            for (int be = 0; be < 4; ++be) {
+                p[4 * al + be] = a.S + (a.L_off + k) * 16 + 4 * al + be;
+                v[4 * al + be] = make_double2(S[al][be].re, S[al][be].im);
+            }
+        ptr_store_group(p, v);
     }
 }
 
@@ -305,6 +361,7 @@ __global__ void k_stoch_contract(StochContractArgs a)
             double2 *o = base + (gi * nt + tt) * Vs + xs;
             double2 cur = *o;
             *o = make_double2(cur.x + acc[q][gi].re, cur.y + acc[q][gi].im);
+            store_drain();  // one store per gamma (their number is a run-time value)
         }
     }
 }
@@ -379,13 +436,17 @@ __device__ void force_link(const ForceArgs &a, int par, int cb, int nf, double s
     }
     double2 *o = a.dU + ((size_t)MU * 2 * g.Vh + lex) * 9;
     double f = a.kappa * sgn;
+    double2 *p[9];
+    double2 w[9];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             // entry (i, j): conj(A_ij) + B_ji
             cx<double> v = cj(A[i][j]) + B[j][i];
             double2 cur = o[3 * i + j];
-            o[3 * i + j] = make_double2(cur.x + f * v.re, cur.y + f * v.im);
+            p[3 * i + j] = o + 3 * i + j;
+            w[3 * i + j] = make_double2(cur.x + f * v.re, cur.y + f * v.im);
         }
+    ptr_store_group(p, w);
 }
 
 __global__ void k_force(ForceArgs a)
@@ -434,10 +495,7 @@ __global__ void k_dot64(const double2 *a, const double2 *b, long long n, double 
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        out2[2 * blockIdx.x] = re[0];
-        out2[2 * blockIdx.x + 1] = im[0];
-    }
+    if (threadIdx.x == 0) ((double2 *)out2)[blockIdx.x] = make_double2(re[0], im[0]);  // one store, ends the kernel
 }
 
 inline unsigned nblk(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }

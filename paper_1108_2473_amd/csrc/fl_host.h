@@ -13,7 +13,24 @@
 // ---------------------------------------------------------------------------
 // kernel argument blocks
 // ---------------------------------------------------------------------------
-enum LinkFormat { LINK_F64_R18 = 0, LINK_F32_R18 = 1, LINK_F32_R12 = 2, LINK_BF16_R12 = 3 };
+// Operator formats of the hopping kernel: link storage, and with it the
+// storage of the spinor fields it reads and writes (FP64 for LINK_F64_R18,
+// 16-bit fixed point for LINK_Q16_R12, FP32 otherwise)
+enum LinkFormat { LINK_F64_R18 = 0, LINK_F32_R18 = 1, LINK_F32_R12 = 2, LINK_BF16_R12 = 3, LINK_Q16_R12 = 4,
+                  LINK_NFMT = 5 };
+enum VecFormat { VEC_F64 = 0, VEC_F32 = 1, VEC_H16 = 2 };
+
+inline VecFormat vec_format(LinkFormat f)
+{
+    return f == LINK_F64_R18 ? VEC_F64 : (f == LINK_Q16_R12 ? VEC_H16 : VEC_F32);
+}
+
+// bytes of one site of one right-hand side of a spinor field / of one link
+inline size_t vec_site_bytes(VecFormat v) { return v == VEC_F64 ? 192 : (v == VEC_F32 ? 96 : 52); }
+inline size_t link_bytes(LinkFormat f)
+{
+    return f == LINK_F64_R18 ? 144 : (f == LINK_F32_R18 ? 72 : (f == LINK_F32_R12 ? 48 : 24));
+}
 
 enum {
     EPI_PLAIN = 0,      // out = cb * H in
@@ -95,7 +112,7 @@ struct BlasArgs {
 
 // precision of the fields of a BLAS launch: FP64 (all fields) or FP32 (all
 // fields except the FP64 "hi" operands named above)
-void launch_blas(bool fp64, const BlasArgs &a, hipStream_t s);
+void launch_blas(VecFormat vf, const BlasArgs &a, hipStream_t s);
 
 enum ScalStep { SC_ALPHA = 0, SC_OMEGA, SC_BETA, SC_RESET, SC_INIT, SC_CG_INIT, SC_CG_ALPHA, SC_CG_BETA };
 
@@ -223,15 +240,15 @@ struct fl_ctx {
     bool have_kappa = false;
     bool have_gauge = false;
     bool su3 = false;  // links are SU(3) to 1e-10 (12-real storage allowed)
-    void *gauge[4] = {nullptr, nullptr, nullptr, nullptr};  // per LinkFormat, built on demand
-    bool gauge_ok[4] = {false, false, false, false};        // packed from the current links
+    void *gauge[LINK_NFMT] = {};     // per LinkFormat, built on demand
+    bool gauge_ok[LINK_NFMT] = {};   // packed from the current links
     double *gauge_canon = nullptr;                          // device copy of the input links
     std::string err;
     std::vector<DevBuf> pool;  // named workspace buffers
     ProfSlot prof[FL_PROF_NKERNELS];
-    int tune_rt[4] = {0, 0, 0, 0};  // per LinkFormat; 0: heuristic
-    int tune_g[4] = {0, 0, 0, 0};
-    int tune_lds[4] = {-1, -1, -1, -1};  // LDS staging mode; -1: built-in choice
+    int tune_rt[LINK_NFMT] = {};                   // per LinkFormat; 0: heuristic
+    int tune_g[LINK_NFMT] = {};
+    int tune_lds[LINK_NFMT] = {-1, -1, -1, -1, -1};  // LDS staging mode; -1: built-in choice
     size_t max_lds = 65536;              // LDS bytes a workgroup may use on this device
 };
 

@@ -34,7 +34,8 @@ struct Solver {
     BatchGeom B;
     int nsys = 0;
     LinkFormat fmt;
-    bool lo64;  // iteration vectors in FP64
+    VecFormat vf;  // storage of the iteration vectors
+    bool lo64;     // iteration vectors in FP64
     hipStream_t st;
     fl_ctx *c0;
     MF RH, T64, R, R0, P, V, S, T, XL, TMP, XH, BH;
@@ -49,7 +50,7 @@ struct Solver {
 
     Solver(SolveBatch &b, const fl_solver_params &p) : sb(b), prm(p) {}
 
-    double lo_bytes_per_site_rhs() const { return lo64 ? 192.0 : 96.0; }
+    double lo_bytes_per_site_rhs() const { return (double)vec_site_bytes(vf); }
 
     void dslash(LinkFormat f, bool lo, int par, const MF &in, const MF &out, const MF *x, const MF *y,
                 double ca, const double *cbv, int epi, int slot0, const int *msk, bool dag, bool prof)
@@ -77,7 +78,7 @@ struct Solver {
         if (prof) prof_end(c0, FL_PROF_DSLASH, 0.0);
     }
 
-    void blas(bool fp64, int op, std::initializer_list<const MF *> fields, int flag, int slot0, const int *msk)
+    void blas(VecFormat f, int op, std::initializer_list<const MF *> fields, int flag, int slot0, const int *msk)
     {
         BlasArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -94,7 +95,7 @@ struct Solver {
             for (int l = 0; l < B.nlat; ++l) a.f[k][l] = f->p[l];
             ++k;
         }
-        launch_blas(fp64, a, st);
+        launch_blas(f, a, st);
     }
 
     void scal(int step, const int *msk)
@@ -122,31 +123,31 @@ struct Solver {
     // one BiCGStab iteration for every active system
     void bicg_iteration()
     {
-        const bool f64 = lo64;
+        const VecFormat lf = vf;
         schur_lo(P, V, EPI_DOTY, &R0, 0, false);                   // v = Dhat p, <r0, v>
         scal(SC_ALPHA, nullptr);
-        blas(f64, OP_BICG_S, {&R, &V, &S}, 0, 0, active);          // s = r - alpha v
+        blas(lf, OP_BICG_S, {&R, &V, &S}, 0, 0, active);          // s = r - alpha v
         schur_lo(S, T, EPI_DOTX_NORM, nullptr, 0, false);           // t = Dhat s, <t, s>, |t|^2
         scal(SC_OMEGA, nullptr);
-        blas(f64, OP_BICG_XR, {&XL, &P, &S, &T, &R, &R0}, 0, 0, active);
+        blas(lf, OP_BICG_XR, {&XL, &P, &S, &T, &R, &R0}, 0, 0, active);
         scal(SC_BETA, nullptr);
-        blas(f64, OP_BICG_P, {&P, &R, &V}, 0, 0, active);          // p = r + beta (p - omega v)
+        blas(lf, OP_BICG_P, {&P, &R, &V}, 0, 0, active);          // p = r + beta (p - omega v)
     }
 
     // CGNR on the Schur system: p, q = Dhat p, z = Dhat^+ r
     void cg_iteration()
     {
-        const bool f64 = lo64;
+        const VecFormat lf = vf;
         // q = Dhat p with |q|^2 (slot 2)
         dslash(fmt, true, 1, P, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, false, true);
         dslash(fmt, true, 0, TMP, V, &P, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, false, false);
         scal(SC_CG_ALPHA, nullptr);
-        blas(f64, OP_CG_XR, {&XL, &R, &P, &V}, 0, 3, active);      // |r|^2 -> slot 5
+        blas(lf, OP_CG_XR, {&XL, &R, &P, &V}, 0, 3, active);      // |r|^2 -> slot 5
         // z = Dhat^+ r with |z|^2 (slot 2)
         dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, true, false);
         dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, true, false);
         scal(SC_CG_BETA, nullptr);
-        blas(f64, OP_CG_P, {&P, &S}, 0, 0, active);
+        blas(lf, OP_CG_P, {&P, &S}, 0, 0, active);
     }
 
     // FP64 residual of the masked systems: rh = bh - Dhat xh (|rh|^2 -> slot 2),
@@ -154,12 +155,12 @@ struct Solver {
     // init = 1 also restarts the recurrence (r0 = p = r, xl = 0)
     void replace_residual(const int *msk, int init)
     {
-        blas(lo64, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                // xh += xl, xl = 0
-        blas(true, OP_SUB_HI, {&RH, &BH, &XH}, 0, 0, msk);           // rh = bh - xh
+        blas(vf, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                  // xh += xl, xl = 0
+        blas(VEC_F64, OP_SUB_HI, {&RH, &BH, &XH}, 0, 0, msk);        // rh = bh - xh
         dslash(LINK_F64_R18, false, 1, XH, T64, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, false, false);
         dslash(LINK_F64_R18, false, 0, T64, RH, &RH, nullptr, 1.0, pos_k2, EPI_XPAY | EPI_NORM, 0, msk, false,
                false);
-        blas(lo64, OP_HI_TO_LO, {&R, &RH, &R0, &P, &XL}, init, 3, msk);
+        blas(vf, OP_HI_TO_LO, {&R, &RH, &R0, &P, &XL}, init, 3, msk);
     }
 
     fl_status run(std::vector<SysResult> &res);
@@ -174,11 +175,14 @@ fl_status Solver::run(std::vector<SysResult> &res)
         fmt = LINK_F64_R18;
     } else if (prm.inner_prec == FL_PREC_F32) {
         fmt = prm.gauge_reals == 18 ? LINK_F32_R18 : LINK_F32_R12;
-    } else {
+    } else if (prm.inner_prec == FL_PREC_BF16) {
         fmt = LINK_BF16_R12;
+    } else {
+        fmt = LINK_Q16_R12;
     }
-    lo64 = fmt == LINK_F64_R18;
-    if (fmt == LINK_F32_R12 || fmt == LINK_BF16_R12)
+    vf = vec_format(fmt);
+    lo64 = vf == VEC_F64;
+    if (fmt == LINK_F32_R12 || fmt == LINK_BF16_R12 || fmt == LINK_Q16_R12)
         for (int l = 0; l < sb.nlat; ++l)
             if (!sb.ctx[l]->su3)
                 return set_err(c0, FL_ERR_ARG, "12-real link storage needs SU(3) links; use gauge_reals = 18");
@@ -193,7 +197,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
     if ((int)sb.bnorm.size() != nsys) return set_err(c0, FL_ERR_ARG, "internal: bnorm size");
 
     // workspace
-    const size_t lob = lo64 ? 192 : 96;
+    const size_t lob = vec_site_bytes(vf);
     for (int l = 0; l < sb.nlat; ++l) {
         fl_ctx *c = sb.ctx[l];
         size_t n = (size_t)sb.nrhs[l] * c->Vh;
@@ -251,7 +255,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
         if ((e = hip_check(c0, hipMemcpyAsync(RH.p[l], BH.p[l], n, hipMemcpyDeviceToDevice, st), "copy b")))
             return e;
     }
-    blas(lo64, OP_HI_TO_LO, {&R, &RH, &R0, &P, &XL}, 1, 3, nullptr);  // r = r0 = p = lo(b), xl = 0
+    blas(vf, OP_HI_TO_LO, {&R, &RH, &R0, &P, &XL}, 1, 3, nullptr);  // r = r0 = p = lo(b), xl = 0
     hact.assign(nsys, 1);
     hmask.assign(nsys, 0);
     if ((e = hip_check(c0, hipMemcpyAsync(active, hact.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
@@ -262,8 +266,8 @@ fl_status Solver::run(std::vector<SysResult> &res)
         dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, true, false);
         dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, msk, true, false);
         scal(SC_CG_INIT, msk);
-        blas(lo64, OP_ZERO, {&P}, 0, 0, msk);
-        blas(lo64, OP_CG_P, {&P, &S}, 0, 0, msk);  // SC_CG_INIT sets beta = 0: p = z
+        blas(vf, OP_ZERO, {&P}, 0, 0, msk);
+        blas(vf, OP_CG_P, {&P, &S}, 0, 0, msk);  // SC_CG_INIT sets beta = 0: p = z
     };
     if (solver == FL_SOLVER_CGNR) {
         cg_start(nullptr);
@@ -295,7 +299,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
         // chunk: a lower bound)
         double bytes = 0;
         for (int l = 0; l < B.nlat; ++l) {
-            int lb = fmt == LINK_F64_R18 ? 144 : (fmt == LINK_F32_R18 ? 72 : (fmt == LINK_F32_R12 ? 48 : 24));
+            const double lb = (double)link_bytes(fmt);
             bytes += 8.0 * lb * B.lat[l].Vh + 2.0 * lo_bytes_per_site_rhs() * B.lat[l].Vh * active_count[l];
         }
         ps.bytes += bytes * nnew;
@@ -437,7 +441,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
     }
     if (trunc) {
         // the LP solution is the low-precision iterate
-        blas(lo64, OP_ACC_HI, {&XH, &XL}, 0, 0, nullptr);
+        blas(vf, OP_ACC_HI, {&XH, &XL}, 0, 0, nullptr);
     }
     fl_status out = FL_OK;
     for (int k = 0; k < nsys; ++k) {

@@ -83,16 +83,19 @@ __device__ __forceinline__ void link_adj_mul(const cx<R> U[3][3], const cx<R> h[
 }
 
 // Where the stencil reads its input spinor field and links from: plain
-// pointers (any lane layout) or per-wave buffer views (scalar resources).
+// pointers (FP64 fields, any lane layout) or per-wave buffer views (scalar
+// resources) of a field stored in format S.  spinor() returns the site's
+// values up to a common factor, which it returns.
 template <typename R, class LK>
 struct PtrSrc {
     const typename SpinorFmt<R>::V *in;
     const typename LK::V *gauge;
     int Vh;
     template <int MU>
-    __device__ __forceinline__ void spinor(int i, cx<R> s[12]) const
+    __device__ __forceinline__ R spinor(int i, cx<R> s[12]) const
     {
         SpinorFmt<R>::load(in, Vh, i, s);
+        return (R)1;
     }
     __device__ __forceinline__ void link(int mu, int par, int i, cx<R> U[3][3]) const
     {
@@ -100,14 +103,15 @@ struct PtrSrc {
     }
 };
 
-template <typename R, class LK>
+template <typename S, class LK>
 struct BufSrc {
+    typedef typename SpinorFmt<S>::R R;
     Buf in, gauge;
     int Vh;
     template <int MU>
-    __device__ __forceinline__ void spinor(int i, cx<R> s[12]) const
+    __device__ __forceinline__ R spinor(int i, cx<R> s[12]) const
     {
-        SpinorFmt<R>::load(in, Vh, i, s);
+        return SpinorFmt<S>::load_raw(in, Vh, i, s);
     }
     __device__ __forceinline__ void link(int mu, int par, int i, cx<R> U[3][3]) const
     {
@@ -122,16 +126,16 @@ __device__ __forceinline__ void hop_dir(int p, int i, int nf, int nb, R sf, R sb
     constexpr int SB = DAG ? -1 : 1;
     cx<R> psi[12], h[6], w[6], U[3][3];
     // forward hop: U_mu(x) psi(x + mu), link stored with the output parity
-    src.template spinor<MU>(nf, psi);
+    const R cf = src.template spinor<MU>(nf, psi);
     project<MU, SF>(psi, h);
     src.link(MU, p, i, U);
-    link_mul(U, h, sf, w);
+    link_mul(U, h, sf * cf, w);
     accumulate<MU, SF>(acc, w);
     // backward hop: U_mu(x - mu)^+ psi(x - mu), link stored at the neighbour
-    src.template spinor<MU>(nb, psi);
+    const R cb = src.template spinor<MU>(nb, psi);
     project<MU, SB>(psi, h);
     src.link(MU, 1 - p, nb, U);
-    link_adj_mul(U, h, sb, w);
+    link_adj_mul(U, h, sb * cb, w);
     accumulate<MU, SB>(acc, w);
 }
 

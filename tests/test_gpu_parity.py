@@ -70,7 +70,7 @@ def test_apply_D_single_rhs_and_device_arrays(F):
 # solver
 # ---------------------------------------------------------------------------
 SOLVERS = [("f64", 0, 18, 0), ("f32r12", 1, 12, 0), ("f32r18", 1, 18, 0), ("bf16r12", 2, 12, 0),
-           ("cgnr-f64", 0, 18, 1), ("cgnr-f32", 1, 12, 1)]
+           ("h16", 3, 12, 0), ("cgnr-f64", 0, 18, 1), ("cgnr-f32", 1, 12, 1), ("cgnr-h16", 3, 12, 1)]
 
 
 @pytest.mark.parametrize("name,prec,reals,solver", SOLVERS)
@@ -107,12 +107,15 @@ def test_solve_zero_and_point_sources(F):
     assert np.abs(x[1:] - xo).max() <= 1e-10 * np.abs(xo).max()
 
 
-def test_truncated_solve_stops_at_its_tolerance(F):
-    """LP solve (truncated): FP32 iteration stopped at |r| <= tol |b|, no FP64 step."""
+@pytest.mark.parametrize("prec", [1, 3])
+def test_truncated_solve_stops_at_its_tolerance(F, prec):
+    """LP solve (truncated): FP32 (or 16-bit storage) iteration stopped at
+    |r| <= tol |b|, no FP64 step; the true residual of the full operator then
+    confirms that the low-precision operator is D to well below tol."""
     dims = (4, 4, 4, 8)
     lat, U = make(F, dims, 0.5, 0.13, -1, 41)
     b = S.random_spinors(dims, 4, 42)
-    x, info = lat.solve(b, F.SolverParams(tol=1e-3, truncated=True, inner_prec=F.PREC_F32))
+    x, info = lat.solve(b, F.SolverParams(tol=1e-3, truncated=True, inner_prec=prec))
     r = b - O.apply_D(U, x, dims, -1, 0.13)
     rel = np.linalg.norm(r.reshape(4, -1), axis=1) / np.linalg.norm(b.reshape(4, -1), axis=1)
     assert np.all(rel <= 1.2e-3), rel
@@ -122,7 +125,7 @@ def test_truncated_solve_stops_at_its_tolerance(F):
 # ---------------------------------------------------------------------------
 # exact loops
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("prec,reals", [(0, 18), (1, 12), (2, 12)])
+@pytest.mark.parametrize("prec,reals", [(0, 18), (1, 12), (2, 12), (3, 12)])
 def test_exact_loops_4x4x4x4(F, prec, reals):
     """The 4^4 workload (eps 0.3, kappa 0.10, antiperiodic time): all 768 point-source
     solves of timeslice 0, every Gamma, against the oracle (e <= 1e-10)."""

@@ -29,14 +29,16 @@ def lattice(F, name, kappa=None):
     return lat, U, W
 
 
-def test_stochastic_16x16x16x32_one_timeslice(F):
+@pytest.mark.parametrize("prec", [1, 3])
+def test_stochastic_16x16x16x32_one_timeslice(F, prec):
     """16^3x32, eps 0.6, kappa 0.1596 (~400 FP64 BiCGStab iterations): a time-diluted
     Z4 source on timeslice 3 through the whole stochastic path (noise, prepare, mixed
-    precision CGNR to 1e-12, reconstruction, contraction) against the oracle."""
+    precision CGNR with FP32 or 16-bit storage to 1e-12, reconstruction,
+    contraction) against the oracle."""
     lat, U, W = lattice(F, "stoch_16x16x16x32")
     q = F.NoiseParams(noise=F.NOISE_Z4, seed=W["noise_seed"], r0=7, n_lp=1, dilution=F.DIL_TIME,
                       t_begin=3, t_end=4)
-    got = lat.loops_stochastic(q, GAMMAS, lp=F.SolverParams(tol=1e-12, solver=F.SOLVER_CGNR))
+    got = lat.loops_stochastic(q, GAMMAS, lp=F.SolverParams(tol=1e-12, solver=F.SOLVER_CGNR, inner_prec=prec))
     want = O.loops_stochastic(U, W["dims"], W["bc_t"], W["kappa"], O.NOISE_Z4, W["noise_seed"], 7, 1,
                               O.DIL_TIME, 3, 4, GAMMAS, tol=1e-13)
     err = np.abs(got - want).max() / np.abs(want[0]).max()
@@ -44,16 +46,18 @@ def test_stochastic_16x16x16x32_one_timeslice(F):
 
 
 def test_solver_16x16x16x32_stopping_rule(F):
-    """Batched mixed-precision solves (BiCGStab and CGNR) of spin-colour-time
-    diluted sources at 16^3x32 meet |Dx-b|/|b| <= 1e-12, recomputed by the oracle."""
+    """Batched mixed-precision solves (BiCGStab and CGNR with FP32 storage, CGNR
+    with 16-bit storage) of spin-colour-time diluted sources at 16^3x32 meet
+    |Dx-b|/|b| <= 1e-12, recomputed by the oracle."""
     lat, U, W = lattice(F, "stoch_16x16x16x32")
     xi = O.noise(O.NOISE_Z4, W["noise_seed"], 0, W["dims"])
     Vs = 16 ** 3
     b = np.zeros((3,) + xi.shape, complex)
     for k, (t, s, c) in enumerate([(0, 0, 0), (11, 2, 1), (31, 3, 2)]):
         b[k, Vs * t:Vs * (t + 1), s, c] = xi[Vs * t:Vs * (t + 1), s, c]
-    for solver in (F.SOLVER_BICGSTAB, F.SOLVER_CGNR):
-        x, info = lat.solve(b, F.SolverParams(tol=1e-12, solver=solver))
+    for solver, prec in ((F.SOLVER_BICGSTAB, F.PREC_F32), (F.SOLVER_CGNR, F.PREC_F32),
+                         (F.SOLVER_CGNR, F.PREC_H16)):
+        x, info = lat.solve(b, F.SolverParams(tol=1e-12, solver=solver, inner_prec=prec))
         r = b - O.apply_D(U, x, W["dims"], W["bc_t"], W["kappa"])
         rel = np.linalg.norm(r.reshape(3, -1), axis=1) / np.linalg.norm(b.reshape(3, -1), axis=1)
         assert np.all(rel <= 1.05e-12), (solver, rel)
