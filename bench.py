@@ -6,9 +6,10 @@ its SESAM ensemble): U = exp(i eps H) with eps = 0.6, kappa = 0.1596 (about
 400 FP64 BiCGStab iterations to 1e-12), antiperiodic time; Z4 noise with
 spin-colour-time dilution, 12 x 32 = 384 diluted sources per noise vector.
 One step = one noise vector: noise generation, even-odd preparation, 384
-batched Schur solves to |Dx-b|/|b| <= 1e-12 (FP32 iteration with FP32
-12-real links, FP64 reliable updates), odd-site reconstruction and the
-contraction of Eq. (loop stochastic) for Gamma = 1, g5, g1..g4.
+batched Schur solves to |Dx-b|/|b| <= 1e-12 (CGNR iteration in FP32
+arithmetic on 16-bit fixed-point vectors and links, FP64 reliable updates;
+--prec f32 stores FP32), odd-site reconstruction and the contraction of
+Eq. (loop stochastic) for Gamma = 1, g5, g1..g4.
 
 Prints one JSON line:  value = diluted solves per second (whole job).
 roofline: the hopping kernel of the iteration (events around every launch
@@ -31,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 counter summary of the hopping kernel timed here (FETCH_SIZE and
 # WRITE_SIZE passes, scaled by a copy kernel of known size); its traffic is
 # reported only while the kernel sources still hash to the recorded value
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hopping_f32r12_stoch_16x16x16x32.md")
+def traffic_profile(prec):
+    return os.path.join(ROOT, "profiles", f"hopping_{prec}r12_stoch_16x16x16x32.md")
 
 
 def kernel_source_hash():
@@ -47,11 +49,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def profiled_traffic():
+def profiled_traffic(prec):
     """HBM bytes per launch from the committed counter summary, or None if the
     summary is missing or was taken on other kernel sources."""
     try:
-        txt = open(TRAFFIC_PROFILE).read()
+        txt = open(traffic_profile(prec)).read()
     except OSError:
         return None
     m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
@@ -79,7 +81,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", choices=["f32", "bf16"], default="f32")
+    ap.add_argument("--prec", choices=["f32", "bf16", "h16"], default="h16")
     ap.add_argument("--batch", type=int, default=384)
     ap.add_argument("--solver", choices=["cgnr", "bicgstab"], default="cgnr")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -107,7 +109,7 @@ def main():
     lat = fl.Lattice(dims, bc, device=0)
     lat.set_gauge(U)
     lat.set_kappa(kappa)
-    prec = fl.PREC_F32 if args.prec == "f32" else fl.PREC_BF16
+    prec = {"f32": fl.PREC_F32, "bf16": fl.PREC_BF16, "h16": fl.PREC_H16}[args.prec]
     solver = fl.SOLVER_CGNR if args.solver == "cgnr" else fl.SOLVER_BICGSTAB
     lp = fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, batch=args.batch, solver=solver)
     nt = dims[3]
@@ -190,7 +192,7 @@ def main():
         log(f"[bench] oracle {t_or:.1f}s ({O.num_threads()} threads); loop rel err vs FP64 {loop_err:.2e}")
 
     bytes_per_launch = prof["bytes"] / max(1, prof["launches"])
-    traffic = profiled_traffic()
+    traffic = profiled_traffic(args.prec)
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -210,13 +212,16 @@ def main():
                         "tol 1e-12 on the full operator, Gamma = 1, g5, g1..g4",
             "lattice": list(dims),
             "solves_per_step": solves_per_step,
-            "inner": f"{args.solver} on the even-odd Schur system, {args.prec} links (12 reals), fp32 vectors, "
-                     "fp64 residual replacement",
+            "inner": f"{args.solver} on the even-odd Schur system, " + {
+                "f32": "fp32 vectors and 12-real links",
+                "bf16": "fp32 vectors, bf16 12-real links",
+                "h16": "16-bit fixed-point vectors (fp32 site scale) and 12-real links"}[args.prec]
+                     + ", fp32 arithmetic, fp64 reliable updates",
             "batch": args.batch,
             "parallelism": "single GPU",
         },
         "roofline": {
-            "kernel": "hopping term H_oe (FP32 12-real links), iteration launches",
+            "kernel": f"hopping term H_oe ({args.prec} storage, 12-real links), iteration launches",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,

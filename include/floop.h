@@ -97,7 +97,10 @@ enum { FL_DIL_TIME = 1, FL_DIL_SPIN = 2, FL_DIL_COLOUR = 4, FL_DIL_EVENODD = 8,
  *  gauge_reals 18 (full links) or 12 (rows 0 and 1; row 2 rebuilt as
  *              conj(row0 x row1)) for the F32 inner operator; BF16 and H16
  *              need 12.
- *  delta       reliable-update trigger in (0, 1); 0 selects 0.1.
+ *  delta       reliable-update trigger in (0, 1); 0 selects 0.1 (0.3 for
+ *              H16).  At a replacement BiCGStab and CGNR keep their search
+ *              directions (CGNR recomputes D^+ r for the replaced r); they
+ *              restart only after a breakdown.
  *  truncated   1: low-precision (LP) solve of the truncated solver method:
  *              inner precision only, stops when the iteration's own
  *              residual reaches tol, no FP64 correction.  The LP map is a

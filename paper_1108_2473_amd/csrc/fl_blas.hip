@@ -324,6 +324,8 @@ __device__ __forceinline__ void scal_step(const ScalArgs &a, const double P[6], 
         }
         s.beta[0] = zn / s.zz;
         s.zz = zn;
+        if (rr > s.rmax2) s.rmax2 = rr;
+        if (rr < s.delta2 * s.rmax2) s.flags |= ST_WANT_UPD;
         if (rr <= s.stop2) {
             s.flags |= ST_CONV_ITER;
             act = 0;
@@ -333,6 +335,16 @@ __device__ __forceinline__ void scal_step(const ScalArgs &a, const double P[6], 
         }
         break;
     }
+    case SC_CG_REZ:  // after a residual replacement that keeps p: slot 2 |z|^2, z = Dhat^+ r; slot 5 |r|^2
+        s.zz = P[2];
+        s.rr = P[5];
+        s.rmax2 = P[5];
+        s.flags &= ~(ST_CONV_ITER | ST_WANT_UPD);
+        if (!(P[2] > 0) || !finite_d(P[2])) {
+            s.flags |= ST_BREAK;
+            act = 0;
+        }
+        break;
     default: break;
     }
 }

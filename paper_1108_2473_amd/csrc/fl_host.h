@@ -114,7 +114,7 @@ struct BlasArgs {
 // fields except the FP64 "hi" operands named above)
 void launch_blas(VecFormat vf, const BlasArgs &a, hipStream_t s);
 
-enum ScalStep { SC_ALPHA = 0, SC_OMEGA, SC_BETA, SC_RESET, SC_INIT, SC_CG_INIT, SC_CG_ALPHA, SC_CG_BETA };
+enum ScalStep { SC_ALPHA = 0, SC_OMEGA, SC_BETA, SC_RESET, SC_INIT, SC_CG_INIT, SC_CG_ALPHA, SC_CG_BETA, SC_CG_REZ };
 
 struct ScalArgs {
     BatchGeom B;
