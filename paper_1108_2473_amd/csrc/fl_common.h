@@ -501,6 +501,7 @@ struct LinkF64R18 {
     static constexpr int REALS = 18;
     static constexpr int BYTES = 144;
     static constexpr int ESZ = 16;
+    static constexpr R UNIT = 1.0;  // unpack() returns the link itself
     __device__ static __forceinline__ void unpack(const V v[NC], cx<double> U[3][3])
     {
 #pragma unroll
@@ -519,6 +520,7 @@ struct LinkF32R18 {
     static constexpr int REALS = 18;
     static constexpr int BYTES = 72;
     static constexpr int ESZ = 8;
+    static constexpr R UNIT = 1.0f;  // unpack() returns the link itself
     __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
     {
 #pragma unroll
@@ -538,6 +540,7 @@ struct LinkF32R12 {
     static constexpr int REALS = 12;
     static constexpr int BYTES = 48;
     static constexpr int ESZ = 16;
+    static constexpr R UNIT = 1.0f;  // unpack() returns the link itself
     __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
     {
 #pragma unroll
@@ -562,6 +565,7 @@ struct LinkBF16R12 {
     static constexpr int REALS = 12;
     static constexpr int BYTES = 24;
     static constexpr int ESZ = 8;
+    static constexpr R UNIT = 1.0f;  // unpack() returns the link itself
     __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
     {
 #pragma unroll
@@ -594,17 +598,20 @@ struct LinkQ16R12 {
     static constexpr int REALS = 12;
     static constexpr int BYTES = 24;
     static constexpr int ESZ = 8;
+    static constexpr R UNIT = 1.0f / 32767.0f;  // unpack() returns 32767 U
     __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
     {
-        constexpr float q = 1.0f / 32767.0f;
+        // rows 0 and 1 as stored (32767 u); row 2 rebuilt from them carries
+        // 32767^2 and is brought to the same 32767 scale
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             int e = 2 * c;
-            cx<float> a = h16_pair(v[c].x), b = h16_pair(v[c].y);
-            U[e / 3][e % 3] = cx<float>{a.re * q, a.im * q};
-            U[(e + 1) / 3][(e + 1) % 3] = cx<float>{b.re * q, b.im * q};
+            U[e / 3][e % 3] = h16_pair(v[c].x);
+            U[(e + 1) / 3][(e + 1) % 3] = h16_pair(v[c].y);
         }
         rebuild_row2(U);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) U[2][b] = cx<float>{U[2][b].re * UNIT, U[2][b].im * UNIT};
     }
     __device__ static __forceinline__ V buf_get(const Buf &g, int voff, int soff)
     {

@@ -110,6 +110,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
 template <typename S, class LK, bool SLINK>
 struct LdsSrc {
     typedef typename SpinorFmt<S>::R R;
+    static constexpr R LINK_UNIT = LK::UNIT;
     Buf in, gauge;
     int Vh, wlo, wsz, wsmax, p, lane;
     const unsigned char *win;

@@ -52,9 +52,43 @@ __device__ __forceinline__ void accumulate(cx<R> acc[12], const cx<R> w[6])
     }
 }
 
-// w = sgn * U h (two spin components)
+// acc += c * v as two FMAs
 template <typename R>
-__device__ __forceinline__ void link_mul(const cx<R> U[3][3], const cx<R> h[6], R sgn, cx<R> w[6])
+__device__ __forceinline__ cx<R> caxpy(cx<R> acc, R c, cx<R> v)
+{
+    return cx<R>{fma(c, v.re, acc.re), fma(c, v.im, acc.im)};
+}
+
+// acc += c * (full 4-spinor of the projected product w), the hop's scalar
+// factor c (boundary sign, storage scales) folded into the FMAs
+template <int MU, int S, typename R>
+__device__ __forceinline__ void accumulate_scaled(cx<R> acc[12], const cx<R> w[6], R c)
+{
+    const R cs = (R)S * c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<R> w0 = w[a], w1 = w[3 + a];
+        acc[a] = caxpy(acc[a], c, w0);
+        acc[3 + a] = caxpy(acc[3 + a], c, w1);
+        if (MU == 0) {
+            acc[6 + a] = caxpy(acc[6 + a], cs, ti(w1));
+            acc[9 + a] = caxpy(acc[9 + a], cs, ti(w0));
+        } else if (MU == 1) {
+            acc[6 + a] = caxpy(acc[6 + a], cs, w1);
+            acc[9 + a] = caxpy(acc[9 + a], -cs, w0);
+        } else if (MU == 2) {
+            acc[6 + a] = caxpy(acc[6 + a], cs, ti(w0));
+            acc[9 + a] = caxpy(acc[9 + a], -cs, ti(w1));
+        } else {
+            acc[6 + a] = caxpy(acc[6 + a], cs, w0);
+            acc[9 + a] = caxpy(acc[9 + a], cs, w1);
+        }
+    }
+}
+
+// w = U h (two spin components)
+template <typename R>
+__device__ __forceinline__ void link_mul(const cx<R> U[3][3], const cx<R> h[6], cx<R> w[6])
 {
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
@@ -63,13 +97,13 @@ __device__ __forceinline__ void link_mul(const cx<R> U[3][3], const cx<R> h[6], 
             cx<R> acc = U[a][0] * h[3 * sp];
             acc = cmad(acc, U[a][1], h[3 * sp + 1]);
             acc = cmad(acc, U[a][2], h[3 * sp + 2]);
-            w[3 * sp + a] = sgn * acc;
+            w[3 * sp + a] = acc;
         }
 }
 
-// w = sgn * U^+ h
+// w = U^+ h
 template <typename R>
-__device__ __forceinline__ void link_adj_mul(const cx<R> U[3][3], const cx<R> h[6], R sgn, cx<R> w[6])
+__device__ __forceinline__ void link_adj_mul(const cx<R> U[3][3], const cx<R> h[6], cx<R> w[6])
 {
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
@@ -78,7 +112,7 @@ __device__ __forceinline__ void link_adj_mul(const cx<R> U[3][3], const cx<R> h[
             cx<R> acc = cjmul(U[0][a], h[3 * sp]);
             acc = cjmad(acc, U[1][a], h[3 * sp + 1]);
             acc = cjmad(acc, U[2][a], h[3 * sp + 2]);
-            w[3 * sp + a] = sgn * acc;
+            w[3 * sp + a] = acc;
         }
 }
 
@@ -88,6 +122,7 @@ __device__ __forceinline__ void link_adj_mul(const cx<R> U[3][3], const cx<R> h[
 // values up to a common factor, which it returns.
 template <typename R, class LK>
 struct PtrSrc {
+    static constexpr R LINK_UNIT = LK::UNIT;
     const typename SpinorFmt<R>::V *in;
     const typename LK::V *gauge;
     int Vh;
@@ -106,6 +141,7 @@ struct PtrSrc {
 template <typename S, class LK>
 struct BufSrc {
     typedef typename SpinorFmt<S>::R R;
+    static constexpr R LINK_UNIT = LK::UNIT;
     Buf in, gauge;
     int Vh;
     template <int MU>
@@ -129,14 +165,14 @@ __device__ __forceinline__ void hop_dir(int p, int i, int nf, int nb, R sf, R sb
     const R cf = src.template spinor<MU>(nf, psi);
     project<MU, SF>(psi, h);
     src.link(MU, p, i, U);
-    link_mul(U, h, sf * cf, w);
-    accumulate<MU, SF>(acc, w);
+    link_mul(U, h, w);
+    accumulate_scaled<MU, SF>(acc, w, sf * cf * SRC::LINK_UNIT);
     // backward hop: U_mu(x - mu)^+ psi(x - mu), link stored at the neighbour
     const R cb = src.template spinor<MU>(nb, psi);
     project<MU, SB>(psi, h);
     src.link(MU, 1 - p, nb, U);
-    link_adj_mul(U, h, sb * cb, w);
-    accumulate<MU, SB>(acc, w);
+    link_adj_mul(U, h, w);
+    accumulate_scaled<MU, SB>(acc, w, sb * cb * SRC::LINK_UNIT);
 }
 
 template <bool DAG, typename R, class SRC>
