@@ -241,6 +241,10 @@ LatGeom lat_geom(const fl_ctx *c, int nrhs)
     g.bc_t = c->bc_t;
     g.nsb = (g.Vh + FL_WAVE - 1) / FL_WAVE;
     g.nrhs = nrhs;
+    g.fLh0 = make_fastdiv((unsigned)g.Lh0);
+    g.fLy = make_fastdiv((unsigned)g.L[1]);
+    g.fLz = make_fastdiv((unsigned)g.L[2]);
+    g.fnsb = make_fastdiv((unsigned)g.nsb);
     return g;
 }
 

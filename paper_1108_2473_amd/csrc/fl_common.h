@@ -502,11 +502,20 @@ struct LinkF64R18 {
     static constexpr int BYTES = 144;
     static constexpr int ESZ = 16;
     static constexpr R UNIT = 1.0;  // unpack() returns the link itself
+    // staged (LDS) form: the stored vectors themselves
+    typedef V SV;
+    static constexpr int SNC = NC;
+    __device__ static __forceinline__ void stage(const V v[NC], SV w[SNC])
+    {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w[c] = v[c];
+    }
     __device__ static __forceinline__ void unpack(const V v[NC], cx<double> U[3][3])
     {
 #pragma unroll
         for (int c = 0; c < 9; ++c) U[c / 3][c % 3] = cx<double>{v[c].x, v[c].y};
     }
+    __device__ static __forceinline__ void unpack_staged(const SV w[SNC], cx<R> U[3][3]) { unpack(w, U); }
     __device__ static __forceinline__ V buf_get(const Buf &g, int voff, int soff)
     {
         return v4f_to_d2(buf_ld16(g, voff, soff));
@@ -521,11 +530,20 @@ struct LinkF32R18 {
     static constexpr int BYTES = 72;
     static constexpr int ESZ = 8;
     static constexpr R UNIT = 1.0f;  // unpack() returns the link itself
+    // staged (LDS) form: the stored vectors themselves
+    typedef V SV;
+    static constexpr int SNC = NC;
+    __device__ static __forceinline__ void stage(const V v[NC], SV w[SNC])
+    {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w[c] = v[c];
+    }
     __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
     {
 #pragma unroll
         for (int c = 0; c < 9; ++c) U[c / 3][c % 3] = cx<float>{v[c].x, v[c].y};
     }
+    __device__ static __forceinline__ void unpack_staged(const SV w[SNC], cx<R> U[3][3]) { unpack(w, U); }
     __device__ static __forceinline__ V buf_get(const Buf &g, int voff, int soff)
     {
         v2f f = buf_ld8(g, voff, soff);
@@ -541,6 +559,14 @@ struct LinkF32R12 {
     static constexpr int BYTES = 48;
     static constexpr int ESZ = 16;
     static constexpr R UNIT = 1.0f;  // unpack() returns the link itself
+    // staged (LDS) form: the stored vectors themselves
+    typedef V SV;
+    static constexpr int SNC = NC;
+    __device__ static __forceinline__ void stage(const V v[NC], SV w[SNC])
+    {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w[c] = v[c];
+    }
     __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
     {
 #pragma unroll
@@ -551,6 +577,7 @@ struct LinkF32R12 {
         }
         rebuild_row2(U);
     }
+    __device__ static __forceinline__ void unpack_staged(const SV w[SNC], cx<R> U[3][3]) { unpack(w, U); }
     __device__ static __forceinline__ V buf_get(const Buf &g, int voff, int soff)
     {
         v4f f = buf_ld16(g, voff, soff);
@@ -566,6 +593,14 @@ struct LinkBF16R12 {
     static constexpr int BYTES = 24;
     static constexpr int ESZ = 8;
     static constexpr R UNIT = 1.0f;  // unpack() returns the link itself
+    // staged (LDS) form: the stored vectors themselves
+    typedef V SV;
+    static constexpr int SNC = NC;
+    __device__ static __forceinline__ void stage(const V v[NC], SV w[SNC])
+    {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w[c] = v[c];
+    }
     __device__ static __forceinline__ void unpack(const V v[NC], cx<float> U[3][3])
     {
 #pragma unroll
@@ -576,6 +611,7 @@ struct LinkBF16R12 {
         }
         rebuild_row2(U);
     }
+    __device__ static __forceinline__ void unpack_staged(const SV w[SNC], cx<R> U[3][3]) { unpack(w, U); }
     __device__ static __forceinline__ V buf_get(const Buf &g, int voff, int soff)
     {
         v2f f = buf_ld8(g, voff, soff);
@@ -618,6 +654,30 @@ struct LinkQ16R12 {
         const v2u u = __builtin_bit_cast(v2u, buf_ld8(g, voff, soff));
         return make_uint2(u.x, u.y);
     }
+    // staged (LDS) form: all nine entries as int16 pairs at the 32767
+    // scale, row 2 rebuilt once per workgroup (its rounding to int16 adds
+    // at most 1/65534 per real, as for the stored rows)
+    typedef unsigned SV;
+    static constexpr int SNC = 9;
+    __device__ static __forceinline__ void stage(const V v[NC], SV w[SNC])
+    {
+        cx<float> U[3][3];
+        unpack(v, U);
+        w[0] = v[0].x;
+        w[1] = v[0].y;
+        w[2] = v[1].x;
+        w[3] = v[1].y;
+        w[4] = v[2].x;
+        w[5] = v[2].y;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            w[6 + b] = h16_pack(U[2][b].re * UNIT, U[2][b].im * UNIT);
+    }
+    __device__ static __forceinline__ void unpack_staged(const SV w[SNC], cx<float> U[3][3])
+    {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) U[e / 3][e % 3] = h16_pair(w[e]);
+    }
 };
 
 // links of (direction mu, parity par) at checkerboard site i
@@ -643,6 +703,30 @@ __device__ __forceinline__ void link_load(const Buf &g, int Vh, int soff0, int i
 // ---------------------------------------------------------------------------
 // geometry of a batch of lattices and the tile map
 // ---------------------------------------------------------------------------
+// Division by a run-time constant d >= 1 for numerators n < 2^31
+// (Granlund and Montgomery 1994): q = (mulhi(m, n) + n) >> l with
+// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1; the sum stays
+// below 2^32 because mulhi(m, n) < n.
+struct FastDiv {
+    unsigned m;
+    int l;
+};
+
+inline FastDiv make_fastdiv(unsigned d)
+{
+    FastDiv f;
+    int s = 0;
+    while ((1ull << s) < d) ++s;
+    f.l = s;
+    f.m = (unsigned)((((1ull << 32) * ((1ull << s) - d)) / d) + 1);
+    return f;
+}
+
+__device__ __forceinline__ int fdiv(int n, FastDiv f)
+{
+    return (int)((__umulhi(f.m, (unsigned)n) + (unsigned)n) >> f.l);
+}
+
 struct LatGeom {
     int L[4];     // extents x, y, z, t
     int Lh0;      // Lx / 2
@@ -653,6 +737,7 @@ struct LatGeom {
     int sys0;     // index of its first right-hand side in per-system arrays
     int tile0;    // first tile of this lattice in the flat grid
     int nrb;      // right-hand-side blocks: ceil(nrhs / RT)
+    FastDiv fLh0, fLy, fLz, fnsb;  // division by Lh0, L[1], L[2], nsb
 };
 
 struct BatchGeom {
@@ -698,13 +783,19 @@ __device__ __forceinline__ TileInfo tile_info(const BatchGeom &B)
     // the site blocks are swept in order with the group's blocks innermost
     int local = tile - g.tile0;
     int G = B.G < g.nrb ? B.G : g.nrb;
-    int span = g.nsb * G;
-    int grp = local / span;
-    int rem = local - grp * span;
-    int Gg = g.nrb - grp * G;
-    if (Gg > G) Gg = G;
-    int sb = rem / Gg;
-    int rb = grp * G + (rem - sb * Gg);
+    int sb, rb;
+    if (G == 1) {  // one right-hand-side block sweeps the site blocks
+        rb = fdiv(local, g.fnsb);
+        sb = local - rb * g.nsb;
+    } else {
+        int span = g.nsb * G;
+        int grp = local / span;
+        int rem = local - grp * span;
+        int Gg = g.nrb - grp * G;
+        if (Gg > G) Gg = G;
+        sb = rem / Gg;
+        rb = grp * G + (rem - sb * Gg);
+    }
     int wave = threadIdx.x / FL_WAVE;
     int lane = threadIdx.x % FL_WAVE;
     TileInfo t;
@@ -727,13 +818,12 @@ struct Coord {
 __device__ __forceinline__ Coord cb_coords(const LatGeom &g, int p, int i)
 {
     Coord c;
-    int xh = i % g.Lh0;
-    c.rest = i / g.Lh0;
-    int r = c.rest;
-    c.y = r % g.L[1];
-    r /= g.L[1];
-    c.z = r % g.L[2];
-    c.t = r / g.L[2];
+    c.rest = fdiv(i, g.fLh0);
+    const int xh = i - c.rest * g.Lh0;
+    const int r = fdiv(c.rest, g.fLy);
+    c.y = c.rest - r * g.L[1];
+    c.t = fdiv(r, g.fLz);
+    c.z = r - c.t * g.L[2];
     c.x = 2 * xh + ((p + c.y + c.z + c.t) & 1);
     return c;
 }

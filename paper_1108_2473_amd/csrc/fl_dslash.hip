@@ -114,7 +114,7 @@ struct LdsSrc {
     Buf in, gauge;
     int Vh, wlo, wsz, wsmax, p, lane;
     const unsigned char *win;
-    const typename LK::V *lk;
+    const typename LK::SV *lk;
     template <int MU>
     __device__ __forceinline__ R spinor(int i, cx<R> s[12]) const
     {
@@ -127,10 +127,10 @@ struct LdsSrc {
     {
         if (SLINK) {
             const int dslot = 2 * mu + (par == p ? 0 : 1);
-            typename LK::V v[LK::NC];
+            typename LK::SV w[LK::SNC];
 #pragma unroll
-            for (int c = 0; c < LK::NC; ++c) v[c] = lk[(dslot * LK::NC + c) * FL_WAVE + lane];
-            LK::unpack(v, U);
+            for (int c = 0; c < LK::SNC; ++c) w[c] = lk[(dslot * LK::SNC + c) * FL_WAVE + lane];
+            LK::unpack_staged(w, U);
         } else {
             link_load<LK>(gauge, Vh, (mu * 2 + par) * LK::NC * Vh * LK::ESZ, i, U);
         }
@@ -160,6 +160,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
 {
     typedef typename SpinorFmt<S>::R R;
     typedef typename LK::V LV;
+    typedef typename LK::SV LSV;
     constexpr int SB = SpinorFmt<S>::SITE_BYTES;
     extern __shared__ unsigned char smem[];
     TileInfo T = tile_info(a.B);
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
     const int wsmax = a.wsmax;
     // wsmax is a multiple of 4, so that every window starts 16-byte aligned
     unsigned char *win = smem + (size_t)wave * SB * wsmax;
-    LV *lk = (LV *)(smem + (size_t)a.B.RT * SB * wsmax);
+    LSV *lk = (LSV *)(smem + (size_t)a.B.RT * SB * wsmax);
     const bool live = T.valid_rhs && !(a.mask && !a.mask[T.sys]);
     const int rhs = __builtin_amdgcn_readfirstlane(T.valid_rhs ? T.rhs : 0);
     const Buf gbuf = make_buf(a.gauge[T.lat], (unsigned)(8u * LK::NC * LK::ESZ * (unsigned)Vh));
@@ -200,8 +201,10 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
 #pragma unroll
                 for (int cc = 0; cc < LK::NC; ++cc) v[cc] = LV{};
             }
+            LSV w[LK::SNC];
+            LK::stage(v, w);
 #pragma unroll
-            for (int cc = 0; cc < LK::NC; ++cc) lk[(dslot * LK::NC + cc) * FL_WAVE + s] = v[cc];
+            for (int cc = 0; cc < LK::SNC; ++cc) lk[(dslot * LK::SNC + cc) * FL_WAVE + s] = w[cc];
         }
     }
     if (live)
@@ -233,7 +236,7 @@ template <typename S, class LK>
 size_t dslash_lds_bytes_t(int RT, int wsmax, int lds)
 {
     size_t b = (size_t)RT * SpinorFmt<S>::SITE_BYTES * wsmax;
-    if (lds == 2) b += (size_t)8 * LK::NC * FL_WAVE * sizeof(typename LK::V);
+    if (lds == 2) b += (size_t)8 * LK::SNC * FL_WAVE * sizeof(typename LK::SV);
     return b;
 }
 
