@@ -230,3 +230,44 @@ def loops_grad(U, dims, bc_t, kappa, t0, gammas, w, tol=1e-13, max_iter=20000, b
     if fails:
         raise RuntimeError(f"oracle: {fails} gradient solves missed tol={tol}")
     return dU, dk.value
+
+
+# ---------------------------------------------------------------------------
+# momentum-projected loops and the disconnected two-point function
+# (Sec. III, Eq. all_dis_corr), written out from their definitions
+# ---------------------------------------------------------------------------
+def momentum_project(L, dims, mom):
+    """Lp[g][k][t] = sum_x exp(+i p_k . x) L[g][t][x] over the spatial sites x
+    of each timeslice, p_k = 2 pi (n_x/Lx, n_y/Ly, n_z/Lz) for the integer
+    vectors n_k = mom[k]; x = (x, y, z) with x fastest in the spatial index
+    xs = x + Lx*(y + Ly*z).  L: complex [ngamma][nt][Vs]."""
+    L = np.asarray(L, dtype=np.complex128)
+    Lx, Ly, Lz = dims[0], dims[1], dims[2]
+    xs = np.arange(Lx * Ly * Lz)
+    x, y, z = xs % Lx, (xs // Lx) % Ly, xs // (Lx * Ly)
+    out = np.zeros((L.shape[0], len(mom), L.shape[1]), dtype=np.complex128)
+    for k, (nx, ny, nz) in enumerate(mom):
+        phase = np.exp(2j * np.pi * (nx * x / Lx + ny * y / Ly + nz * z / Lz))
+        for g in range(L.shape[0]):
+            for t in range(L.shape[1]):
+                out[g, k, t] = np.sum(phase * L[g, t])
+    return out
+
+
+def disconnected_correlator(Lp1, Lp2, Vs, pairs):
+    """D[j][k][t] = (1/Vs) (1/T) sum_{ti} Lp1[A_j][k][(ti + t) mod T] Lp2[B_j][k][ti]
+    for pairs j = (A_j, B_j): Lp1 projected with +p_k, Lp2 with -p_k, both over
+    all T timeslices (time translation average of Eq. all_dis_corr; with
+    independent stochastic estimates in Lp1 and Lp2 the product is unbiased)."""
+    Lp1 = np.asarray(Lp1, dtype=np.complex128)
+    Lp2 = np.asarray(Lp2, dtype=np.complex128)
+    T = Lp1.shape[2]
+    D = np.zeros((len(pairs), Lp1.shape[1], T), dtype=np.complex128)
+    for j, (A, B) in enumerate(pairs):
+        for k in range(Lp1.shape[1]):
+            for t in range(T):
+                acc = 0j
+                for ti in range(T):
+                    acc += Lp1[A, k, (ti + t) % T] * Lp2[B, k, ti]
+                D[j, k, t] = acc / (Vs * T)
+    return D
