@@ -140,8 +140,9 @@ def main():
     lat.profile_enable(fl.PROF_DSLASH, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    loops = []
     for k in range(args.steps):
-        step(k)
+        loops.append(step(k))
         log(f"[bench] step {k} done at {time.perf_counter() - t0:.2f}s")
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
@@ -152,6 +153,32 @@ def main():
     avg_us = prof["ms"] * 1e3 / max(1, prof["launches"])
     log(f"[bench] {value:.1f} solves/s; hopping kernel {prof['launches']} launches, avg {avg_us:.1f} us, "
         f"{achieved:.0f} GB/s")
+
+    # disconnected two-point function (Eq. all_dis_corr) from the timed steps
+    # loops: two independent noise vectors, 33 momenta with |n|^2 <= 3, all
+    # Gamma pairs (A, A); projections and correlator timed after the step
+    corr = None
+    if len(loops) >= 2:
+        mom = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+        mom += [(2, 0, 0), (0, 2, 0), (0, 0, 2), (-2, 0, 0), (0, -2, 0), (0, 0, -2)]
+        neg = [(-a, -b, -c) for a, b, c in mom]
+        L1 = torch.from_numpy(loops[0]).cuda()
+        L2 = torch.from_numpy(loops[1]).cuda()
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        P1 = lat.momentum_project(L1, mom)
+        P2 = lat.momentum_project(L2, neg)
+        tp = time.perf_counter()
+        D = lat.disconnected_corr(P1, P2, [(g, g) for g in range(len(gam))])
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        d0 = D[1, mom.index((0, 0, 0))].real.cpu().numpy()  # gamma_5 - gamma_5, p = 0
+        corr = {"momenta": len(mom), "gamma_pairs": len(gam),
+                "projection_us_per_loop_set": round((tp - tc) * 1e6 / 2, 1),
+                "correlator_us": round((td - tp) * 1e6, 1),
+                "D_g5g5_p0_t0_3": [float(x) for x in d0[:4]]}
+        log(f"[bench] momentum projection {corr['projection_us_per_loop_set']} us per loop set, "
+            f"correlator {corr['correlator_us']} us")
 
     if args.timed_only:
         print(json.dumps({"metric": METRIC, "value": round(value, 3), "unit": "solves/s", "steps": args.steps,
@@ -254,6 +281,7 @@ def main():
         "speedup_vs_fp64_single_rhs": round(value / fp64_rate, 3),
         "loop_rel_err_vs_fp64": loop_err,
         "iterations": {"fp64_single": info64[0]["iters"], "mixed": info_mp[0]["iters"]},
+        "disconnected_correlator": corr,
     }
     print(json.dumps(out), flush=True)
 

@@ -266,6 +266,29 @@ fl_status fl_set_tile(fl_ctx *ctx, int prec, int gauge_reals, int rt, int group,
 fl_status fl_autotune(fl_ctx *ctx, int prec, int gauge_reals, int nrhs, int *rt, int *group,
                       int *lds, double *ms);
 
+/* Momentum projection of loops (Sec. III, Eq. all_dis_corr):
+ *   Lp[g][k][t] = sum_x exp(+i p_k . x) L[g][t][x],
+ *   p_k = 2 pi (n_x / Lx, n_y / Ly, n_z / Lz)  for the integer vector
+ *   n_k = (mom[3k], mom[3k+1], mom[3k+2]) (any sign).
+ * L: [ngamma][nt][V_s][2] doubles (loops on any nt timeslices, e.g. the
+ * output of fl_loops_exact or fl_loops_stochastic; site x = (x, y, z) with x
+ * fastest), Lp: [ngamma][nmom][nt][2]; 1 <= ngamma <= 16.  L and Lp are
+ * both on the host or both on the device (`where`); mom is a host array.
+ * Needs no gauge field.  FP64, summed in a fixed order (deterministic). */
+fl_status fl_momentum_project(fl_ctx *ctx, const double *L, int ngamma, int nt, const int *mom,
+                              int nmom, double *Lp, fl_where where);
+
+/* Disconnected two-point function (Sec. III, Eq. all_dis_corr), averaged
+ * over the source timeslice ti:
+ *   D[j][k][t] = (1/V_s) (1/T) sum_ti Lp1[A_j][k][(ti + t) mod T] * Lp2[B_j][k][ti]
+ * Lp1, Lp2: [ngamma][nmom][T][2], loops on all T timeslices projected with
+ * +p_k (Lp1) and -p_k (Lp2) by fl_momentum_project; pairs: npair host pairs
+ * (A_j, B_j) of Gamma indices; D: [npair][nmom][T][2].  For stochastic loops
+ * Lp1 and Lp2 must come from independent noise vectors: the product of one
+ * estimate with itself is biased.  Lp1, Lp2 and D follow `where`. */
+fl_status fl_disconnected_corr(fl_ctx *ctx, const double *Lp1, const double *Lp2, int ngamma,
+                               int nmom, const int *pairs, int npair, double *D, fl_where where);
+
 /* Text of the last error of ctx (or of the last failed fl_create when ctx
  * is NULL). */
 const char *fl_last_error(const fl_ctx *ctx);

@@ -136,11 +136,13 @@ def lib():
     L.fl_bench_dslash.argtypes = [vp, i, i, i, i, i, i, i, i, dp, dp]
     L.fl_set_tile.argtypes = [vp, i, i, i, i, i]
     L.fl_autotune.argtypes = [vp, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), dp]
+    L.fl_momentum_project.argtypes = [vp, vp, i, i, ctypes.POINTER(i), i, vp, i]
+    L.fl_disconnected_corr.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(i), i, vp, i]
     L.fl_solver_params_default.argtypes = [ctypes.POINTER(_SolverParams)]
     for name in ("fl_create", "fl_destroy", "fl_set_stream", "fl_set_gauge", "fl_set_kappa", "fl_apply_D",
                  "fl_solve", "fl_loops_exact", "fl_loops_exact_sites", "fl_loops_stochastic",
                  "fl_loops_stochastic_multi", "fl_loops_grad", "fl_profile_enable", "fl_profile_read",
-                 "fl_bench_dslash", "fl_set_tile", "fl_autotune"):
+                 "fl_bench_dslash", "fl_set_tile", "fl_autotune", "fl_momentum_project", "fl_disconnected_corr"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -312,6 +314,35 @@ class Lattice:
             self._h, sites.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), sites.size, g_arr, ng,
             ctypes.byref(params.c()), ctypes.c_void_p(lp), ctypes.c_void_p(sp) if want_S else None, where))
         return (L, S) if want_S else L
+
+    def momentum_project(self, L, mom):
+        """Lp[g][k][t] = sum_x exp(+i p_k.x) L[g][t][x] for integer momentum vectors
+        mom[k] = (n_x, n_y, n_z), p = 2 pi n / L (Eq. all_dis_corr).  L: [ngamma][nt][Vs]
+        (numpy or a torch complex128 cuda tensor; the result follows it)."""
+        a = _Arr(L)
+        ng, nt = a.shape[0], a.shape[1]
+        if a.shape[2] != self.Vs:
+            raise ValueError(f"loops must have {self.Vs} spatial sites")
+        m = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+        out, optr = _empty_like_where(a, (ng, m.shape[0], nt))
+        self._check(lib().fl_momentum_project(self._h, ctypes.c_void_p(a.ptr), ng, nt,
+                                              m.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), m.shape[0],
+                                              ctypes.c_void_p(optr), a.where))
+        return out
+
+    def disconnected_corr(self, Lp1, Lp2, pairs):
+        """D[j][k][t] = (1/Vs)(1/T) sum_ti Lp1[A_j][k][ti+t] Lp2[B_j][k][ti] (Eq. all_dis_corr):
+        Lp1 projected with +p, Lp2 with -p, both over all T timeslices."""
+        a1, a2 = _Arr(Lp1), _Arr(Lp2)
+        if a1.shape != a2.shape or a1.where != a2.where:
+            raise ValueError("Lp1 and Lp2 must have the same shape and location")
+        ng, nm, T = a1.shape
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        out, optr = _empty_like_where(a1, (pr.shape[0], nm, T))
+        self._check(lib().fl_disconnected_corr(self._h, ctypes.c_void_p(a1.ptr), ctypes.c_void_p(a2.ptr), ng, nm,
+                                               pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), pr.shape[0],
+                                               ctypes.c_void_p(optr), a1.where))
+        return out
 
     def loops_stochastic(self, noise: NoiseParams, gammas, lp: SolverParams = None,
                          hp: SolverParams = None, device=False):
