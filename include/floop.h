@@ -289,6 +289,32 @@ fl_status fl_momentum_project(fl_ctx *ctx, const double *L, int ngamma, int nt, 
 fl_status fl_disconnected_corr(fl_ctx *ctx, const double *Lp1, const double *Lp2, int ngamma,
                                int nmom, const int *pairs, int npair, double *D, fl_where where);
 
+/* Gaussian smearing of quark fields (Sec. III), in place:
+ *   psi <- F psi,  F = ((1 + alpha H) / norm)^n,
+ *   H(x, y) = sum_{i=1..3} [U_i(x) delta_{x,y-i} + U_i(x-i)^+ delta_{x,y+i}]
+ * with the context's links (pass APE-smeared links to it for the paper's
+ * setup), colour only, within each timeslice.  norm = 1 is the paper's F;
+ * norm = 1 + 6 alpha keeps the field of order one over n = 50 steps.
+ * psi: [nrhs][V][4][3][2] doubles on the host or the device (`where`).
+ * FP64. */
+fl_status fl_smear(fl_ctx *ctx, double *psi, int nrhs, double alpha, int n, double norm,
+                   fl_where where);
+
+/* Connected pseudoscalar two-point function (Sec. III, Eq. all_corr with
+ * Gamma_A = Gamma_B = g5) from a point source at lexicographic site y0,
+ * smeared at the source and/or the sink with F of fl_smear:
+ *   C[k][t] = sum_x exp(+i p_k.(x - y0)) sum_{b, beta} |phi_{b,beta}(x, t0 + t)|^2,
+ *   phi = F_sink D^-1 F_source e_{y0, b, beta}  (g5-hermiticity),
+ * t counted from the source timeslice t0 (mod T); mom: nmom integer vectors
+ * (host); C: [nmom][T][2] on the host or the device (`where`).  The 12
+ * solves use params p (stopping rule on the full operator).  With local
+ * fields (no smearing) and the disconnected part D(t) of
+ * fl_disconnected_corr at p = 0 and Gamma = g5, the flavour-singlet
+ * correlator of two degenerate flavours is C_pi(t) - 2 D(t). */
+fl_status fl_pion_corr(fl_ctx *ctx, long long y0, const fl_solver_params *p, double alpha, int n,
+                       double norm, int smear_source, int smear_sink, const int *mom, int nmom,
+                       double *C, fl_where where);
+
 /* Text of the last error of ctx (or of the last failed fl_create when ctx
  * is NULL). */
 const char *fl_last_error(const fl_ctx *ctx);

@@ -137,12 +137,15 @@ def lib():
     L.fl_set_tile.argtypes = [vp, i, i, i, i, i]
     L.fl_autotune.argtypes = [vp, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), dp]
     L.fl_momentum_project.argtypes = [vp, vp, i, i, ctypes.POINTER(i), i, vp, i]
+    L.fl_smear.argtypes = [vp, vp, i, d, i, d, i]
+    L.fl_pion_corr.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(_SolverParams), d, i, d, i, i,
+                               ctypes.POINTER(i), i, vp, i]
     L.fl_disconnected_corr.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(i), i, vp, i]
     L.fl_solver_params_default.argtypes = [ctypes.POINTER(_SolverParams)]
     for name in ("fl_create", "fl_destroy", "fl_set_stream", "fl_set_gauge", "fl_set_kappa", "fl_apply_D",
                  "fl_solve", "fl_loops_exact", "fl_loops_exact_sites", "fl_loops_stochastic",
                  "fl_loops_stochastic_multi", "fl_loops_grad", "fl_profile_enable", "fl_profile_read",
-                 "fl_bench_dslash", "fl_set_tile", "fl_autotune", "fl_momentum_project", "fl_disconnected_corr"):
+                 "fl_bench_dslash", "fl_set_tile", "fl_autotune", "fl_momentum_project", "fl_disconnected_corr", "fl_smear", "fl_pion_corr"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -328,6 +331,32 @@ class Lattice:
         self._check(lib().fl_momentum_project(self._h, ctypes.c_void_p(a.ptr), ng, nt,
                                               m.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), m.shape[0],
                                               ctypes.c_void_p(optr), a.where))
+        return out
+
+    def smear(self, psi, alpha=4.0, n=50, norm=1.0):
+        """F psi with F = ((1 + alpha H)/norm)^n (Gaussian smearing, Sec. III); psi [nrhs][V][4][3]
+        (numpy: a smeared copy is returned; torch cuda: smeared in place and returned)."""
+        a = _Arr(psi)
+        if a.torch:
+            self._check(lib().fl_smear(self._h, ctypes.c_void_p(a.ptr), a.shape[0], float(alpha), int(n),
+                                       float(norm), a.where))
+            return a.obj
+        out = np.array(a.obj, copy=True)
+        self._check(lib().fl_smear(self._h, ctypes.c_void_p(out.ctypes.data), out.shape[0], float(alpha), int(n),
+                                   float(norm), FL_HOST))
+        return out
+
+    def pion_corr(self, y0, params: SolverParams = None, alpha=4.0, n=50, norm=1.0, smear_source=True,
+                  smear_sink=True, mom=((0, 0, 0),)):
+        """Connected pseudoscalar two-point function C[k][t] from a point source at site y0
+        (Eq. all_corr, g5-hermiticity), smeared at source and/or sink, t from the source time."""
+        params = params or SolverParams()
+        m = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+        out = np.empty((m.shape[0], self.dims[3]), dtype=np.complex128)
+        self._check(lib().fl_pion_corr(self._h, int(y0), ctypes.byref(params.c()), float(alpha), int(n),
+                                       float(norm), int(bool(smear_source)), int(bool(smear_sink)),
+                                       m.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), m.shape[0],
+                                       ctypes.c_void_p(out.ctypes.data), FL_HOST))
         return out
 
     def disconnected_corr(self, Lp1, Lp2, pairs):

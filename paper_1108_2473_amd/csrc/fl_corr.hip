@@ -97,6 +97,13 @@ unsigned blocks(long long n) { return (unsigned)((n + BLK - 1) / BLK); }
 
 }  // namespace
 
+void launch_momproj(const double2 *L, double2 *Lp, const int *dmom, int ngamma, int nt, int nmom, const int L4[4],
+                    hipStream_t s)
+{
+    MomArgs a{L, Lp, dmom, ngamma, nt, nmom, L4[0], L4[1], L4[2], L4[0] * L4[1] * L4[2]};
+    hipLaunchKernelGGL(k_momproj, dim3((unsigned)(nt * nmom)), dim3(BLK), 0, s, a);
+}
+
 fl_status fl_momentum_project(fl_ctx *c, const double *L, int ngamma, int nt, const int *mom, int nmom, double *Lp,
                               fl_where where)
 {
@@ -122,8 +129,7 @@ fl_status fl_momentum_project(fl_ctx *c, const double *L, int ngamma, int nt, co
         din = bi;
         dout = bo;
     }
-    MomArgs a{din, dout, dmom, ngamma, nt, nmom, c->L[0], c->L[1], c->L[2], Vs};
-    hipLaunchKernelGGL(k_momproj, dim3((unsigned)(nt * nmom)), dim3(BLK), 0, c->stream, a);
+    launch_momproj(din, dout, dmom, ngamma, nt, nmom, c->L, c->stream);
     if ((e = hip_check(c, hipGetLastError(), "momentum projection"))) return e;
     if (where == FL_HOST &&
         (e = hip_check(c, hipMemcpyAsync(Lp, dout, nout, hipMemcpyDeviceToHost, c->stream), "download")))

@@ -142,6 +142,10 @@ void launch_pack_links(const double *canon, void *dst, LinkFormat fmt, const Lat
 void launch_su3_check(const double *canon, double *dev_max, long long nlinks, hipStream_t s);
 
 // point sources: rhs j = 12*k + 3*spin + colour at lexicographic site sites[k]
+// momentum projection Lp[g][k][t] = sum_x exp(i p_k.x) L[g][t][x] (device
+// arrays; dmom: device [nmom][3]) on stream s
+void launch_momproj(const double2 *L, double2 *Lp, const int *dmom, int ngamma, int nt, int nmom, const int L4[4],
+                    hipStream_t s);
 void launch_point_sources(double2 *even, double2 *odd, const long long *sites, int nsites,
                           const LatGeom &g, hipStream_t s);
 
@@ -275,7 +279,8 @@ enum {
     WS_CANON = 0, WS_BE, WS_BO, WS_XE, WS_XO, WS_BH, WS_RH, WS_T64, WS_R, WS_R0, WS_P, WS_V, WS_S,
     WS_T, WS_XL, WS_TMP, WS_PART, WS_STATE, WS_ACTIVE, WS_MASK, WS_SITES, WS_GAM, WS_ACC,
     WS_ACC2, WS_COMP, WS_M, WS_CE, WS_CO, WS_DU, WS_HE, WS_HO, WS_XE2, WS_XO2, WS_MISC,
-    WS_CORR_A, WS_CORR_B, WS_CORR_OUT, WS_CORR_IDX,
+    WS_CORR_A, WS_CORR_B, WS_CORR_OUT, WS_CORR_IDX, WS_SM_E0, WS_SM_O0, WS_SM_E1, WS_SM_O1, WS_PI_SRC,
+    WS_PI_SOL, WS_PI_RHO,
     WS_NSLOTS
 };
 
