@@ -352,3 +352,47 @@ def pion_correlator(U, dims, bc_t, kappa, y0, mom, alpha=0.0, n=0, norm=1.0, sme
         for t in range(T):
             C[k, t] = ph * P[k, (t0 + t) % T]
     return C
+
+
+# ---------------------------------------------------------------------------
+# the paper's comparison of stochastic methods with the exact loops (Sec. IV),
+# composed from the oracle's own loops, projection and correlator
+# ---------------------------------------------------------------------------
+def dilution_study(configs, dims, bc_t, kappa, n_noise, schemes, tsm, seed, tol_hp, tol_lp, tol_exact=1e-13):
+    """D(t) at p = 0 for Gamma = g5 per configuration: exact (point sources on
+    every site), plain stochastic with complex Z2 noise for each dilution mask
+    in `schemes` (name -> mask) and N noise vectors (unbiased mean over pairs
+    r != s of per-vector loops), and the truncated solver method for each
+    (n_lp, n_hp) in `tsm` (two independent halves correlated with each other;
+    half h starts at noise index h (n_lp + n_hp) / 2 of seed + 1).
+    Configuration c uses seed + 1000 c.  Returns dicts of [nconf][T] arrays."""
+    T = dims[3]
+    Vs = dims[0] * dims[1] * dims[2]
+    zero = [(0, 0, 0)]
+    out = {"exact": [], "stochastic": {}, "tsm": {}}
+    for ci, U in enumerate(configs):
+        cseed = seed + 1000 * ci
+        Lx = loops_exact(U, dims, bc_t, kappa, list(range(T)), [15], tol=tol_exact)
+        P = momentum_project(Lx, dims, zero)
+        out["exact"].append(disconnected_correlator(P, P, Vs, [(0, 0)])[0, 0])
+        for name, mask in schemes.items():
+            per = [momentum_project(loops_stochastic(U, dims, bc_t, kappa, NOISE_CZ2, cseed, r, 1, mask, 0, T,
+                                                     [15], tol=tol_hp), dims, zero)[0]
+                   for r in range(max(n_noise))]
+            for N in n_noise:
+                acc = np.zeros(T, dtype=np.complex128)
+                for r in range(N):
+                    for s in range(N):
+                        if r != s:
+                            acc += disconnected_correlator(per[r][None], per[s][None], Vs, [(0, 0)])[0, 0]
+                out["stochastic"].setdefault((name, N), []).append(acc / (N * (N - 1)))
+        for (n_lp, n_hp) in tsm:
+            halves = [momentum_project(loops_tsm(U, dims, bc_t, kappa, NOISE_CZ2, cseed + 1, h * (n_lp + n_hp) // 2,
+                                                 n_lp // 2, n_hp // 2, tol_lp, tol_hp, 0, 0, T, [15]), dims, zero)
+                      for h in range(2)]
+            out["tsm"].setdefault((n_lp, n_hp), []).append(
+                disconnected_correlator(halves[0], halves[1], Vs, [(0, 0)])[0, 0])
+    out["exact"] = np.array(out["exact"])
+    out["stochastic"] = {k: np.array(v) for k, v in out["stochastic"].items()}
+    out["tsm"] = {k: np.array(v) for k, v in out["tsm"].items()}
+    return out
