@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--prec", choices=["f32", "bf16", "h16"], default="h16")
     ap.add_argument("--batch", type=int, default=384)
     ap.add_argument("--solver", choices=["cgnr", "bicgstab"], default="cgnr")
+    ap.add_argument("--delta", type=float, default=0.0, help="reliable-update trigger (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-rhs", type=int, default=4, help="single-RHS FP64 GPU solves for the reference rate")
     ap.add_argument("--timed-only", action="store_true",
@@ -118,7 +119,8 @@ def main():
     lat.set_kappa(kappa)
     prec = {"f32": fl.PREC_F32, "bf16": fl.PREC_BF16, "h16": fl.PREC_H16}[args.prec]
     solver = fl.SOLVER_CGNR if args.solver == "cgnr" else fl.SOLVER_BICGSTAB
-    lp = fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, batch=args.batch, solver=solver)
+    lp = fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, batch=args.batch, solver=solver,
+                         delta=args.delta)
     nt = dims[3]
     solves_per_step = 12 * nt
 
@@ -143,7 +145,8 @@ def main():
     loops = []
     for k in range(args.steps):
         loops.append(step(k))
-        log(f"[bench] step {k} done at {time.perf_counter() - t0:.2f}s")
+        log(f"[bench] step {k} done at {time.perf_counter() - t0:.2f}s "
+            f"({lat.profile_read(fl.PROF_DSLASH)['launches']} hopping launches so far)")
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     prof = lat.profile_read(fl.PROF_DSLASH)

@@ -151,7 +151,8 @@ typedef struct {
 } fl_noise_params;
 
 /* Fill p with defaults: BiCGStab, tol 1e-12, max_iter 20000, FP32 inner
- * with 12-real links, delta 0.1, not truncated, default batch. */
+ * with 12-real links, delta 0 (the solver's default for the inner
+ * precision), not truncated, default batch. */
 void fl_solver_params_default(fl_solver_params *p);
 
 /* Library version string. */

@@ -64,7 +64,7 @@ class SolverParams:
     max_iter: int = 20000
     inner_prec: int = PREC_F32
     gauge_reals: int = 12
-    delta: float = 0.1
+    delta: float = 0.0  # 0: the library default (0.1; 0.3 for 16-bit storage)
     truncated: bool = False
     batch: int = 0
 

@@ -369,7 +369,7 @@ void fl_solver_params_default(fl_solver_params *p)
     p->max_iter = 20000;
     p->inner_prec = FL_PREC_F32;
     p->gauge_reals = 12;
-    p->delta = 0.1;
+    p->delta = 0.0;  // the solver picks its default for the inner precision
     p->truncated = 0;
     p->batch = 0;
 }

@@ -43,7 +43,7 @@ def test_version_and_defaults(lib):
     p = fl._SolverParams()
     lib.fl_solver_params_default(ctypes.byref(p))
     assert p.solver == 0 and p.tol == 1e-12 and p.gauge_reals == 12 and p.inner_prec == fl.PREC_F32
-    assert 0 < p.delta < 1 and p.truncated == 0
+    assert p.delta == 0.0 and p.truncated == 0  # 0: the solver chooses delta for the inner precision
 
 
 def test_argument_checks_before_any_device_call(lib):
