@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--batch", type=int, default=384)
     ap.add_argument("--solver", choices=["cgnr", "bicgstab"], default="cgnr")
     ap.add_argument("--delta", type=float, default=0.0, help="reliable-update trigger (0: the library default)")
+    ap.add_argument("--lds", type=int, default=-1,
+                    help="LDS mode of the hopping kernel (-1: the library default; 3: packed 16-bit hop)")
+    ap.add_argument("--rt", type=int, default=0, help="right-hand sides per workgroup (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-rhs", type=int, default=4, help="single-RHS FP64 GPU solves for the reference rate")
     ap.add_argument("--timed-only", action="store_true",
@@ -121,6 +124,8 @@ def main():
     solver = fl.SOLVER_CGNR if args.solver == "cgnr" else fl.SOLVER_BICGSTAB
     lp = fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, batch=args.batch, solver=solver,
                          delta=args.delta)
+    if args.lds != -1 or args.rt:
+        lat.set_tile(prec=prec, gauge_reals=12, rt=args.rt, group=0, lds=args.lds)
     nt = dims[3]
     solves_per_step = 12 * nt
 
@@ -282,6 +287,8 @@ def main():
                 "h16": "16-bit fixed-point vectors (fp32 site scale) and 12-real links"}[args.prec]
                      + ", fp32 arithmetic, fp64 reliable updates",
             "batch": args.batch,
+            "lds_mode": args.lds,
+            "rt": args.rt,
             "parallelism": "single GPU",
         },
         "roofline": {

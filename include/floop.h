@@ -183,6 +183,19 @@ fl_status fl_set_kappa(fl_ctx *ctx, double kappa);
 fl_status fl_apply_D(fl_ctx *ctx, const double *in, double *out, int nrhs, int dagger,
                      fl_where where);
 
+/* The even-odd Schur operator Dhat = 1 - kappa^2 H_eo H_oe (dagger = 1:
+ * Dhat^+ = g5 Dhat g5) as the solvers apply it, in the iteration precision
+ * and link storage of p (inner_prec, gauge_reals; p->batch bounds the
+ * right-hand sides per launch, the other fields are not used): the even
+ * sites of each of the nrhs canonical FP64 spinors in `in` are rounded to
+ * that storage, the two hops and the vector update run in its arithmetic,
+ * and the even sites of `out` (canonical FP64, nrhs spinors) receive the
+ * result widened to FP64; odd sites of `out` are set to 0 and odd sites of
+ * `in` are not read.  The hopping-kernel shape and LDS mode of
+ * fl_set_tile() apply.  Operator of the Schur system solved in Sec. III. */
+fl_status fl_apply_schur(fl_ctx *ctx, const double *in, double *out, int nrhs, int dagger,
+                         const fl_solver_params *p, fl_where where);
+
 /* Solve D x_k = b_k for nrhs right-hand sides (canonical spinor layout)
  * to the stopping rule of Sec. III, via the Schur system
  * x_e = (1 - k^2 H_eo H_oe)^{-1} (b_e + k H_eo b_o), x_o = b_o + k H_oe x_e.
@@ -256,8 +269,11 @@ fl_status fl_bench_dslash(fl_ctx *ctx, int prec, int gauge_reals, int nrhs, int 
  * uses at most 8), `group` right-hand-side blocks that sweep the site
  * blocks together (0: all), and lds, the LDS staging of the hopping kernel:
  * 0 none, 1 each wavefront's x/y neighbour window, 2 windows plus the
- * workgroup's links, -1 the built-in choice (2 when it fits).  rt = 0
- * restores the built-in workgroup size. */
+ * workgroup's links, 3 (FL_PREC_H16 only) as 2 with the hop computed on the
+ * stored 16-bit integers (packed int16 spin projection, exact int16 dot
+ * products for the colour product, links staged at half scale), -1 the
+ * built-in choice (2 when it fits).  rt = 0 restores the built-in workgroup
+ * size.  FL_ERR_ARG for out-of-range values or lds 3 with another precision. */
 fl_status fl_set_tile(fl_ctx *ctx, int prec, int gauge_reals, int rt, int group, int lds);
 
 /* Autotuner: time the hopping kernel for nrhs right-hand sides over the

@@ -119,6 +119,7 @@ def lib():
     L.fl_set_gauge.argtypes = [vp, vp, i]
     L.fl_set_kappa.argtypes = [vp, d]
     L.fl_apply_D.argtypes = [vp, vp, vp, i, i, i]
+    L.fl_apply_schur.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(_SolverParams), i]
     L.fl_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(_SolverParams), ctypes.POINTER(_SolverStats), i]
     L.fl_loops_exact.argtypes = [vp, ctypes.POINTER(i), i, ctypes.POINTER(i), i,
                                  ctypes.POINTER(_SolverParams), vp, vp, i]
@@ -143,7 +144,7 @@ def lib():
     L.fl_disconnected_corr.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(i), i, vp, i]
     L.fl_solver_params_default.argtypes = [ctypes.POINTER(_SolverParams)]
     for name in ("fl_create", "fl_destroy", "fl_set_stream", "fl_set_gauge", "fl_set_kappa", "fl_apply_D",
-                 "fl_solve", "fl_loops_exact", "fl_loops_exact_sites", "fl_loops_stochastic",
+                 "fl_apply_schur", "fl_solve", "fl_loops_exact", "fl_loops_exact_sites", "fl_loops_stochastic",
                  "fl_loops_stochastic_multi", "fl_loops_grad", "fl_profile_enable", "fl_profile_read",
                  "fl_bench_dslash", "fl_set_tile", "fl_autotune", "fl_momentum_project", "fl_disconnected_corr", "fl_smear", "fl_pion_corr"):
         getattr(L, name).restype = i
@@ -265,6 +266,17 @@ class Lattice:
         self._stream_for(a)
         self._check(lib().fl_apply_D(self._h, ctypes.c_void_p(a.ptr), ctypes.c_void_p(optr), nrhs,
                                      int(dagger), a.where))
+        return out
+
+    def apply_schur(self, psi, params: SolverParams = None, dagger=False):
+        """Dhat = 1 - kappa^2 H_eo H_oe on the even sites of psi, computed in the
+        iteration precision and link storage of params (odd sites of the result 0)."""
+        params = params or SolverParams()
+        a, nrhs = self._spinors(psi)
+        out, optr = _empty_like_where(a, a.shape)
+        self._stream_for(a)
+        self._check(lib().fl_apply_schur(self._h, ctypes.c_void_p(a.ptr), ctypes.c_void_p(optr), nrhs,
+                                         int(dagger), ctypes.byref(params.c()), a.where))
         return out
 
     def solve(self, b, params: SolverParams = None, check=True):

@@ -301,8 +301,10 @@ void dslash_config(const fl_ctx *c, LinkFormat fmt, DslashArgs &a)
     a.wsmax = (ws + 3) & ~3;  // 16-byte aligned windows for every site format
     int mode = c->tune_lds[fmt];
     // built-in (measured at 16^3x32): FP32 windows and staged links, FP64
-    // windows only; a mode that does not fit the LDS falls back to the next
-    if (mode < 0) mode = fmt == LINK_F64_R18 ? 1 : 2;
+    // windows only, 16-bit fields the packed hop with staged links and no
+    // windows; a mode that does not fit the LDS falls back to the next
+    if (mode < 0) mode = fmt == LINK_F64_R18 ? 1 : (fmt == LINK_Q16_R12 ? 4 : 2);
+    if (mode >= 3 && fmt != LINK_Q16_R12) mode = 2;  // the packed integer hop is for 16-bit fields only
     while (mode > 0 && dslash_lds_bytes(fmt, a.B.RT, a.wsmax, mode) > c->max_lds) --mode;
     a.lds = mode;
 }
@@ -524,6 +526,53 @@ fl_status fl_apply_D(fl_ctx *c, const double *in, double *out, int nrhs, int dag
         if ((e = hip_check(c, hipStreamSynchronize(c->stream), "apply D"))) return e;
     }
     return hip_check(c, hipGetLastError(), "apply D");
+}
+
+fl_status fl_apply_schur(fl_ctx *c, const double *in, double *out, int nrhs, int dagger,
+                         const fl_solver_params *p, fl_where where)
+{
+    if (!valid_ctx(c)) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
+    if (nrhs < 0 || (nrhs > 0 && (!in || !out))) return set_err(c, FL_ERR_ARG, "bad spinor arguments");
+    fl_status e;
+    if ((e = check_ready(c))) return e;
+    if ((e = check_params(c, p))) return e;
+    hipSetDevice(c->device);
+    const int chunk = std::max(1, std::min(nrhs, p->batch > 0 ? p->batch : default_batch(c, 1)));
+    const size_t per = (size_t)c->V * 24 * sizeof(double);
+    for (int k0 = 0; k0 < nrhs; k0 += chunk) {
+        int n = std::min(chunk, nrhs - k0);
+        const double *src = in + (size_t)k0 * c->V * 24;
+        double *dst = out + (size_t)k0 * c->V * 24;
+        double *cin = (double *)src, *cout = dst;
+        if (where == FL_HOST) {
+            cin = (double *)ws_get(c, WS_CANON, per * n);
+            cout = cin;
+            if (!cin) return set_err(c, FL_ERR_NOMEM, "device allocation failed");
+            if ((e = hip_check(c, hipMemcpyAsync(cin, src, per * n, hipMemcpyHostToDevice, c->stream), "upload")))
+                return e;
+        }
+        size_t fb = (size_t)n * c->Vh * 192;
+        void *be = ws_get(c, WS_BE, fb), *bo = ws_get(c, WS_BO, fb);
+        void *xe = ws_get(c, WS_XE, fb), *xo = ws_get(c, WS_XO, fb);
+        if (!be || !bo || !xe || !xo) return set_err(c, FL_ERR_NOMEM, "device allocation failed");
+        LatGeom g = lat_geom(c, n);
+        launch_canon_to_eo(cin, (double2 *)be, (double2 *)bo, g, n, c->stream);
+        SolveBatch sb;
+        sb.nlat = 1;
+        sb.ctx[0] = c;
+        sb.nrhs[0] = n;
+        sb.bh[0] = (const double2 *)be;
+        sb.xh[0] = (double2 *)xe;
+        sb.bnorm.assign(n, 1.0);
+        if ((e = schur_apply_batch(sb, *p, dagger != 0))) return e;
+        if ((e = hip_check(c, hipMemsetAsync(xo, 0, fb, c->stream), "memset"))) return e;
+        launch_eo_to_canon((double2 *)xe, (double2 *)xo, cout, g, n, c->stream);
+        if (where == FL_HOST)
+            if ((e = hip_check(c, hipMemcpyAsync(dst, cout, per * n, hipMemcpyDeviceToHost, c->stream), "download")))
+                return e;
+        if ((e = hip_check(c, hipStreamSynchronize(c->stream), "apply Schur operator"))) return e;
+    }
+    return hip_check(c, hipGetLastError(), "apply Schur operator");
 }
 
 fl_status fl_solve(fl_ctx *c, const double *b, double *x, int nrhs, const fl_solver_params *p,
@@ -1222,15 +1271,16 @@ fl_status fl_bench_dslash(fl_ctx *c, int prec, int gauge_reals, int nrhs, int nr
     if ((e = check_ready(c))) return e;
     LinkFormat fmt;
     if ((e = fmt_of(c, prec, gauge_reals, &fmt))) return e;
-    if (lds < -1 || lds > 2) return set_err(c, FL_ERR_ARG, "lds must be -1, 0, 1 or 2");
+    if (lds < -1 || lds > 4 || (lds >= 3 && fmt != LINK_Q16_R12))
+        return set_err(c, FL_ERR_ARG, "lds must be -1, 0, 1 or 2 (3, 4: 16-bit fields only)");
     return bench_impl(c, fmt, nrhs, nrep, nsets, rt, group, lds, ms_per_launch, bytes_per_launch);
 }
 
 fl_status fl_set_tile(fl_ctx *c, int prec, int gauge_reals, int rt, int group, int lds)
 {
     if (!valid_ctx(c)) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
-    if (rt < 0 || rt > 16 || (rt & (rt - 1)) || group < 0 || lds < -1 || lds > 2)
-        return set_err(c, FL_ERR_ARG, "rt must be 0 or a power of two <= 16, group >= 0, lds in -1..2");
+    if (rt < 0 || rt > 16 || (rt & (rt - 1)) || group < 0 || lds < -1 || lds > 4)
+        return set_err(c, FL_ERR_ARG, "rt must be 0 or a power of two <= 16, group >= 0, lds in -1..4");
     LinkFormat fmt;
     if (prec == FL_PREC_F64 && gauge_reals == 18)
         fmt = LINK_F64_R18;
@@ -1242,6 +1292,7 @@ fl_status fl_set_tile(fl_ctx *c, int prec, int gauge_reals, int rt, int group, i
         fmt = LINK_Q16_R12;
     else
         return set_err(c, FL_ERR_ARG, "unsupported precision / link storage");
+    if (lds >= 3 && fmt != LINK_Q16_R12) return set_err(c, FL_ERR_ARG, "lds 3 and 4 need 16-bit fields");
     c->tune_rt[fmt] = rt;
     c->tune_g[fmt] = group;
     c->tune_lds[fmt] = lds;
@@ -1260,7 +1311,8 @@ fl_status fl_autotune(fl_ctx *c, int prec, int gauge_reals, int nrhs, int *rt_ou
     const int maxrt = fmt == LINK_F64_R18 ? 8 : 16;
     double best = 1e300;
     int brt = 0, bg = 0, bl = 0;
-    for (int lds = 0; lds <= 2; ++lds)
+    const int maxlds = fmt == LINK_Q16_R12 ? 4 : 2;
+    for (int lds = 0; lds <= maxlds; ++lds)
         for (int rt = 1; rt <= maxrt; rt *= 2) {
             if (rt > 1 && rt / 2 >= nrhs) break;
             int nrb = (nrhs + rt - 1) / rt;

@@ -363,6 +363,24 @@ __device__ __forceinline__ unsigned h16_pack(float a, float b)
     return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pknorm_i16(a, b));
 }
 
+// a complex number as two int16 in one 32-bit word (real part low)
+typedef short s2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s2 as_s2(unsigned w) { return __builtin_bit_cast(s2, w); }
+__device__ __forceinline__ s2 swp(s2 z) { return __builtin_shufflevector(z, z, 1, 0); }
+
+// the 12 stored words of a site, each int16 halved (arithmetic shift)
+__device__ __forceinline__ void h16_halve(const v4u u[3], s2 p[12])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        p[4 * c] = as_s2(u[c].x) >> (s2){1, 1};
+        p[4 * c + 1] = as_s2(u[c].y) >> (s2){1, 1};
+        p[4 * c + 2] = as_s2(u[c].z) >> (s2){1, 1};
+        p[4 * c + 3] = as_s2(u[c].w) >> (s2){1, 1};
+    }
+}
+
 template <>
 struct SpinorFmt<H16> {
     typedef float R;
@@ -440,6 +458,44 @@ struct SpinorFmt<H16> {
 #pragma unroll
         for (int c = 0; c < 3; ++c) v[c] = ((const v4f *)w)[c * wsmax + j];
         unpack(v, s);
+        return ((const float *)(w + (size_t)3 * 16 * wsmax))[j];
+    }
+    // integer forms for the packed hop: the stored integers halved, and the
+    // site's scale (a value is 2 * scale * halved integer, up to the
+    // rounding of the halving)
+    __device__ static __forceinline__ float load_half(const Buf &b, int Vh, int i, s2 p[12])
+    {
+        v4u u[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u[c] = __builtin_bit_cast(v4u, buf_ld16(b, i * 16, c * Vh * 16));
+        const float sc = buf_ld4(b, i * 4, 3 * Vh * 16);
+        h16_halve(u, p);
+        return sc;
+    }
+    // LDS window of halved integers, laid out as to_lds()
+    __device__ static __forceinline__ void to_lds_half(const Buf &b, int Vh, int i, unsigned char *w, int wsmax,
+                                                       int j)
+    {
+        s2 p[12];
+        const float sc = load_half(b, Vh, i, p);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            ((v4u *)w)[c * wsmax + j] = v4u{__builtin_bit_cast(unsigned, p[4 * c]),
+                                            __builtin_bit_cast(unsigned, p[4 * c + 1]),
+                                            __builtin_bit_cast(unsigned, p[4 * c + 2]),
+                                            __builtin_bit_cast(unsigned, p[4 * c + 3])};
+        ((float *)(w + (size_t)3 * 16 * wsmax))[j] = sc;
+    }
+    __device__ static __forceinline__ float lds_load_i16(const unsigned char *w, int wsmax, int j, s2 p[12])
+    {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const v4u u = ((const v4u *)w)[c * wsmax + j];
+            p[4 * c] = as_s2(u.x);
+            p[4 * c + 1] = as_s2(u.y);
+            p[4 * c + 2] = as_s2(u.z);
+            p[4 * c + 3] = as_s2(u.w);
+        }
         return ((const float *)(w + (size_t)3 * 16 * wsmax))[j];
     }
 };
@@ -677,6 +733,32 @@ struct LinkQ16R12 {
     {
 #pragma unroll
         for (int e = 0; e < 9; ++e) U[e / 3][e % 3] = h16_pair(w[e]);
+    }
+    // staged form of the packed integer hop: at half scale, round(16383.5 u)
+    // (|entry| <= 16384), each entry as the two int16 pairs whose dot
+    // products with a colour component h = (hr, hi) give the real and the
+    // imaginary part of the product: for the link itself (forward hop)
+    //   u h:        (ur, -ui) . h,   (ui, ur) . h
+    // and for its adjoint (backward hop), entry (a, b) of U^+ = conj(u_ba):
+    //   conj(u) h:  (ur, ui) . h,    (-ui, ur) . h
+    // in words 2e, 2e + 1 of entry e = 3a + b of the matrix applied
+    static constexpr float HALF_UNIT = 2.0f / 32767.0f;
+    static constexpr int PK_SNC = 18;
+    __device__ static __forceinline__ void stage_pk(const V v[NC], bool adj, SV w[PK_SNC])
+    {
+        cx<float> U[3][3];
+        unpack(v, U);
+        const float k = 0.5f * UNIT;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const cx<float> u = adj ? U[b][a] : U[a][b];
+                const float ur = u.re * k, ui = u.im * k;
+                const int e = 3 * a + b;
+                w[2 * e] = adj ? h16_pack(ur, ui) : h16_pack(ur, -ui);
+                w[2 * e + 1] = adj ? h16_pack(-ui, ur) : h16_pack(ui, ur);
+            }
     }
 };
 

@@ -20,6 +20,8 @@
 // (RT right-hand sides of the same 64 sites, which share the link loads in
 // L1).  The epilogue fuses the vector update and the reductions that the
 // Krylov iteration needs right after the operator.
+#include <type_traits>
+
 #include "fl_host.h"
 #include "fl_stencil.h"
 
@@ -110,6 +112,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
 template <typename S, class LK, bool SLINK>
 struct LdsSrc {
     typedef typename SpinorFmt<S>::R R;
+    static constexpr bool PACKED_I16 = false;
     static constexpr R LINK_UNIT = LK::UNIT;
     Buf in, gauge;
     int Vh, wlo, wsz, wsmax, p, lane;
@@ -137,6 +140,34 @@ struct LdsSrc {
     }
 };
 
+// Source of the packed integer hop (16-bit fields, lds mode 3): x/y
+// neighbours from the wave's LDS window of halved integers, z/t neighbours
+// from memory (halved on load), links from the workgroup's half-scale
+// staging.  The factor returned with a site's integers is its scale times 2
+// (the halving) times the staged link unit.
+template <bool WIN>
+struct LdsSrcQ16 {
+    static constexpr bool PACKED_I16 = true;
+    Buf in;
+    int Vh, wlo, wsmax, lane;
+    const unsigned char *win;
+    const unsigned *lk;
+    template <int MU>
+    __device__ __forceinline__ float spinor_i16(int i, s2 p[12]) const
+    {
+        constexpr float k = 2.0f * LinkQ16R12::HALF_UNIT;
+        if (WIN && MU < 2)
+            return k * SpinorFmt<H16>::lds_load_i16(win, wsmax, i - wlo, p);
+        else
+            return k * SpinorFmt<H16>::load_half(in, Vh, i, p);
+    }
+    __device__ __forceinline__ void link_i16(int dslot, unsigned L[18]) const
+    {
+#pragma unroll
+        for (int c = 0; c < LinkQ16R12::PK_SNC; ++c) L[c] = lk[(dslot * LinkQ16R12::PK_SNC + c) * FL_WAVE + lane];
+    }
+};
+
 // checkerboard index of the backward neighbour x - mu of site (p, i)
 __device__ __forceinline__ int back_neighbour(const LatGeom &g, const Coord &c, int mu)
 {
@@ -155,9 +186,13 @@ __device__ __forceinline__ int back_neighbour(const LatGeom &g, const Coord &c, 
     return xh + Lh0 * (c.y + Ly * (c.z + Lz * tb));
 }
 
-template <typename S, class LK, bool DAG, int EPI, bool SLINK>
+// SLINK: links staged in LDS; PK (16-bit fields only, with SLINK): the
+// packed integer hop on halved windows and half-scale staged links;
+// NOWIN: no neighbour windows (x/y neighbours from memory like z/t)
+template <typename S, class LK, bool DAG, int EPI, bool SLINK, bool PK = false, bool NOWIN = false>
 __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024) void k_dslash_lds(DslashArgs a)
 {
+    static_assert(!PK || (SLINK && std::is_same<LK, LinkQ16R12>::value), "packed hop needs staged Q16 links");
     typedef typename SpinorFmt<S>::R R;
     typedef typename LK::V LV;
     typedef typename LK::SV LSV;
@@ -175,7 +210,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
     const int wsmax = a.wsmax;
     // wsmax is a multiple of 4, so that every window starts 16-byte aligned
     unsigned char *win = smem + (size_t)wave * SB * wsmax;
-    LSV *lk = (LSV *)(smem + (size_t)a.B.RT * SB * wsmax);
+    LSV *lk = (LSV *)(NOWIN ? smem : smem + (size_t)a.B.RT * SB * wsmax);
     const bool live = T.valid_rhs && !(a.mask && !a.mask[T.sys]);
     const int rhs = __builtin_amdgcn_readfirstlane(T.valid_rhs ? T.rhs : 0);
     const Buf gbuf = make_buf(a.gauge[T.lat], (unsigned)(8u * LK::NC * LK::ESZ * (unsigned)Vh));
@@ -201,32 +236,56 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
 #pragma unroll
                 for (int cc = 0; cc < LK::NC; ++cc) v[cc] = LV{};
             }
-            LSV w[LK::SNC];
-            LK::stage(v, w);
+            if constexpr (PK) {
+                LSV w[LK::PK_SNC];
+                LK::stage_pk(v, (dslot & 1) != 0, w);
 #pragma unroll
-            for (int cc = 0; cc < LK::SNC; ++cc) lk[(dslot * LK::SNC + cc) * FL_WAVE + s] = w[cc];
+                for (int cc = 0; cc < LK::PK_SNC; ++cc) lk[(dslot * LK::PK_SNC + cc) * FL_WAVE + s] = w[cc];
+            } else {
+                LSV w[LK::SNC];
+                LK::stage(v, w);
+#pragma unroll
+                for (int cc = 0; cc < LK::SNC; ++cc) lk[(dslot * LK::SNC + cc) * FL_WAVE + s] = w[cc];
+            }
         }
     }
-    if (live)
-        for (int j = lane; j < wsz; j += FL_WAVE) SpinorFmt<S>::to_lds(ibuf, Vh, wlo + j, win, wsmax, j);
+    if (live && !NOWIN)
+        for (int j = lane; j < wsz; j += FL_WAVE) {
+            if constexpr (PK)
+                SpinorFmt<S>::to_lds_half(ibuf, Vh, wlo + j, win, wsmax, j);
+            else
+                SpinorFmt<S>::to_lds(ibuf, Vh, wlo + j, win, wsmax, j);
+        }
     __syncthreads();
     if (!live) return;
     R q0 = 0, q1 = 0, q2 = 0;
     if (T.valid_site) {
         Coord c = cb_coords(g, a.par, T.site);
-        LdsSrc<S, LK, SLINK> src;
-        src.in = ibuf;
-        src.gauge = gbuf;
-        src.Vh = Vh;
-        src.wlo = wlo;
-        src.wsz = wsz;
-        src.wsmax = wsmax;
-        src.p = a.par;
-        src.lane = lane;
-        src.win = win;
-        src.lk = lk;
         cx<R> acc[12];
-        hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
+        if constexpr (PK) {
+            LdsSrcQ16<!NOWIN> src;
+            src.in = ibuf;
+            src.Vh = Vh;
+            src.wlo = wlo;
+            src.wsmax = wsmax;
+            src.lane = lane;
+            src.win = win;
+            src.lk = (const unsigned *)lk;
+            hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
+        } else {
+            LdsSrc<S, LK, SLINK> src;
+            src.in = ibuf;
+            src.gauge = gbuf;
+            src.Vh = Vh;
+            src.wlo = wlo;
+            src.wsz = wsz;
+            src.wsmax = wsmax;
+            src.p = a.par;
+            src.lane = lane;
+            src.win = win;
+            src.lk = lk;
+            hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
+        }
         epilogue<S, EPI>(a, T, g, rhs, acc, q0, q1, q2);
     }
     reduce_partials<EPI>(a, T, q0, q1, q2);
@@ -235,8 +294,10 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
 template <typename S, class LK>
 size_t dslash_lds_bytes_t(int RT, int wsmax, int lds)
 {
-    size_t b = (size_t)RT * SpinorFmt<S>::SITE_BYTES * wsmax;
+    size_t b = lds == 4 ? 0 : (size_t)RT * SpinorFmt<S>::SITE_BYTES * wsmax;
     if (lds == 2) b += (size_t)8 * LK::SNC * FL_WAVE * sizeof(typename LK::SV);
+    if constexpr (std::is_same<LK, LinkQ16R12>::value)
+        if (lds >= 3) b += (size_t)8 * LK::PK_SNC * FL_WAVE * sizeof(typename LK::SV);
     return b;
 }
 
@@ -247,7 +308,17 @@ void launch_one(const DslashArgs &a, dim3 grid, dim3 block, hipStream_t s)
         hipLaunchKernelGGL((k_dslash<S, LK, DAG, EPI>), grid, block, 0, s, a);
     } else {
         size_t shm = dslash_lds_bytes_t<S, LK>(a.B.RT, a.wsmax, a.lds);
-        if (a.lds == 2)
+        if constexpr (std::is_same<LK, LinkQ16R12>::value) {
+            if (a.lds == 3) {
+                hipLaunchKernelGGL((k_dslash_lds<S, LK, DAG, EPI, true, true>), grid, block, shm, s, a);
+                return;
+            }
+            if (a.lds == 4) {
+                hipLaunchKernelGGL((k_dslash_lds<S, LK, DAG, EPI, true, true, true>), grid, block, shm, s, a);
+                return;
+            }
+        }
+        if (a.lds >= 2)
             hipLaunchKernelGGL((k_dslash_lds<S, LK, DAG, EPI, true>), grid, block, shm, s, a);
         else
             hipLaunchKernelGGL((k_dslash_lds<S, LK, DAG, EPI, false>), grid, block, shm, s, a);

@@ -304,3 +304,6 @@ struct SysResult {
 
 fl_status solve_schur_batch(SolveBatch &sb, const fl_solver_params &p,
                             std::vector<SysResult> &res);
+// xh = Dhat bh (dag: Dhat^+ bh) for every system of the batch, computed in
+// the iteration precision and link storage of p
+fl_status schur_apply_batch(SolveBatch &sb, const fl_solver_params &p, bool dag);

@@ -31,7 +31,8 @@ struct MF {  // one field per lattice
 struct Solver {
     SolveBatch &sb;
     const fl_solver_params &prm;
-    BatchGeom B;
+    BatchGeom B;    // launches in the iteration precision
+    BatchGeom B64;  // FP64 launches (reliable updates): at most 8 waves per workgroup
     int nsys = 0;
     LinkFormat fmt;
     VecFormat vf;  // storage of the iteration vectors
@@ -57,7 +58,7 @@ struct Solver {
     {
         DslashArgs a;
         std::memset(&a, 0, sizeof(a));
-        a.B = B;
+        a.B = f == LINK_F64_R18 ? B64 : B;
         a.par = par;
         a.slot0 = slot0;
         a.nsys = nsys;
@@ -82,7 +83,7 @@ struct Solver {
     {
         BlasArgs a;
         std::memset(&a, 0, sizeof(a));
-        a.B = B;
+        a.B = f == VEC_F64 ? B64 : B;
         a.op = op;
         a.flag = flag;
         a.slot0 = slot0;
@@ -163,14 +164,16 @@ struct Solver {
         blas(vf, OP_HI_TO_LO, {&R, &RH, &R0, &P, &XL}, init, 3, msk);
     }
 
+    fl_status prepare();
     fl_status run(std::vector<SysResult> &res);
+    fl_status apply(bool dag);
 };
 
-fl_status Solver::run(std::vector<SysResult> &res)
+// precision, batch geometry and workspace of the batch
+fl_status Solver::prepare()
 {
     c0 = sb.ctx[0];
     st = c0->stream;
-    const int solver = prm.solver;
     if (prm.inner_prec == FL_PREC_F64) {
         fmt = LINK_F64_R18;
     } else if (prm.inner_prec == FL_PREC_F32) {
@@ -191,10 +194,11 @@ fl_status Solver::run(std::vector<SysResult> &res)
     int RT, G;
     tile_shape(c0, fmt, minr, &RT, &G);
     B = batch_geom(sb.ctx, sb.nrhs, sb.nlat, RT, G);
+    // the FP64 kernels are built for at most 512 threads per workgroup
+    B64 = RT > 8 ? batch_geom(sb.ctx, sb.nrhs, sb.nlat, 8, G) : B;
     nsys = 0;
     for (int l = 0; l < sb.nlat; ++l) nsys += sb.nrhs[l];
     if (nsys == 0) return FL_OK;
-    if ((int)sb.bnorm.size() != nsys) return set_err(c0, FL_ERR_ARG, "internal: bnorm size");
 
     // workspace
     const size_t lob = vec_site_bytes(vf);
@@ -226,10 +230,41 @@ fl_status Solver::run(std::vector<SysResult> &res)
     active = (int *)ws_get(c0, WS_ACTIVE, sizeof(int) * nsys);
     mask = (int *)ws_get(c0, WS_MASK, sizeof(int) * nsys);
     if (!partial || !dst || !active || !mask) return set_err(c0, FL_ERR_NOMEM, "device allocation failed");
+    return hip_check(c0, hipMemsetAsync(partial, 0, sizeof(double) * 6 * (size_t)nsys * B.nsb_max, st), "memset");
+}
+
+// xh = Dhat bh (dag: Dhat^+ bh) with the operator and vectors in the
+// iteration precision: bh rounded to the iteration format, the two hops of
+// the Schur operator, the result widened to FP64
+fl_status Solver::apply(bool dag)
+{
     fl_status e;
-    if ((e = hip_check(c0, hipMemsetAsync(partial, 0, sizeof(double) * 6 * (size_t)nsys * B.nsb_max, st),
-                       "memset")))
+    if ((e = prepare())) return e;
+    if (nsys == 0) return FL_OK;
+    hact.assign(nsys, 1);
+    if ((e = hip_check(c0, hipMemcpyAsync(active, hact.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
+                       "upload active")))
         return e;
+    for (int l = 0; l < sb.nlat; ++l) {
+        size_t n = (size_t)sb.nrhs[l] * sb.ctx[l]->Vh * 192;
+        if ((e = hip_check(c0, hipMemcpyAsync(RH.p[l], BH.p[l], n, hipMemcpyDeviceToDevice, st), "copy b")))
+            return e;
+        if ((e = hip_check(c0, hipMemsetAsync(XH.p[l], 0, n, st), "memset x"))) return e;
+    }
+    blas(vf, OP_HI_TO_LO, {&R, &RH, &R0, &P, &XL}, 0, 3, nullptr);  // r = lo(b)
+    schur_lo(R, V, 0, nullptr, 0, dag);
+    blas(vf, OP_ACC_HI, {&XH, &V}, 0, 0, nullptr);  // xh = v
+    if ((e = hip_check(c0, hipStreamSynchronize(st), "apply Schur operator"))) return e;
+    return hip_check(c0, hipGetLastError(), "apply Schur operator");
+}
+
+fl_status Solver::run(std::vector<SysResult> &res)
+{
+    fl_status e;
+    if ((e = prepare())) return e;
+    if (nsys == 0) return FL_OK;
+    if ((int)sb.bnorm.size() != nsys) return set_err(c0, FL_ERR_ARG, "internal: bnorm size");
+    const int solver = prm.solver;
 
     // initial state
     const double tol = prm.tol;
@@ -333,6 +368,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
                            "download active")))
             return e;
         if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
+        if ((e = hip_check(c0, hipGetLastError(), "solver launch"))) return e;
         for (int l = 0; l < sb.nlat; ++l) active_count[l] = 0;
         for (int k = 0; k < nsys; ++k)
             if (hact[k]) active_count[sys_lat(k)]++;
@@ -381,6 +417,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
                                "download state")))
                 return e;
             if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
+            if ((e = hip_check(c0, hipGetLastError(), "solver launch"))) return e;
             for (int k = 0; k < nsys; ++k)
                 if (restart[k]) {
                     hst[k].flags = 0;
@@ -397,6 +434,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
                                "download active")))
                 return e;
             if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
+            if ((e = hip_check(c0, hipGetLastError(), "solver launch"))) return e;
         }
         if (any_upd) {
             if ((e = hip_check(c0, hipMemcpyAsync(mask, hmask.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
@@ -408,6 +446,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
                                "download state")))
                 return e;
             if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
+            if ((e = hip_check(c0, hipGetLastError(), "solver launch"))) return e;
             for (int k = 0; k < nsys; ++k) {
                 if (!hmask[k]) continue;
                 res[k].updates++;
@@ -472,4 +511,10 @@ fl_status solve_schur_batch(SolveBatch &sb, const fl_solver_params &p, std::vect
 {
     Solver s(sb, p);
     return s.run(res);
+}
+
+fl_status schur_apply_batch(SolveBatch &sb, const fl_solver_params &p, bool dag)
+{
+    Solver s(sb, p);
+    return s.apply(dag);
 }

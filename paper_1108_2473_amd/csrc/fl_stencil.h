@@ -116,12 +116,83 @@ __device__ __forceinline__ void link_adj_mul(const cx<R> U[3][3], const cx<R> h[
         }
 }
 
+// ---------------------------------------------------------------------------
+// Packed 16-bit integer form of one hop, for fields stored as 16-bit fixed
+// point: the spin projection runs as packed int16 adds on the stored
+// integers and the colour product as exact int16 dot products summed in
+// int32 (v_dot2_i32_i16), converted to FP32 once per product component.
+// The neighbour's integers are halved first (arithmetic shift), so that no
+// projected component leaves the int16 range (|u| + |l| <= 2 * 16384), and
+// the links are staged at half scale, round(16383.5 u), which keeps every
+// three-term sum of a product row below sqrt(6) * 32768 * 16384 < 2^31
+// (Cauchy-Schwarz over the 6 reals of a unit row of U or U^+ and the 6
+// reals of a projected colour vector).  Each staged entry carries the two
+// int16 pairs that give the real and the imaginary part of its product with
+// a colour component directly, so a lane forms no conjugate or swapped copy
+// of anything.  A complex number is one 32-bit word, real part in the low
+// half.
+// ---------------------------------------------------------------------------
+// the projection of project<MU, S> on halved integers; i z = swp(z) * (-1, 1)
+template <int MU, int S>
+__device__ __forceinline__ void project_i16(const s2 p[12], s2 h[6])
+{
+    constexpr short s = (short)S, n = (short)-S;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const s2 u0 = p[a], u1 = p[3 + a], l0 = p[6 + a], l1 = p[9 + a];
+        if (MU == 0) {
+            h[a] = u0 + swp(l1) * (s2){s, n};      // u0 - s i l1
+            h[3 + a] = u1 + swp(l0) * (s2){s, n};  // u1 - s i l0
+        } else if (MU == 1) {
+            h[a] = u0 + l1 * (s2){n, n};
+            h[3 + a] = u1 + l0 * (s2){s, s};
+        } else if (MU == 2) {
+            h[a] = u0 + swp(l0) * (s2){s, n};      // u0 - s i l0
+            h[3 + a] = u1 + swp(l1) * (s2){n, s};  // u1 + s i l1
+        } else {
+            h[a] = u0 + l0 * (s2){s, s};
+            h[3 + a] = u1 + l1 * (s2){s, s};
+        }
+    }
+}
+
+// u . h (the products summed exactly in int32) as the three-operand form with
+// an inline zero accumulator: the builtin with a zero accumulator becomes
+// the two-operand v_dot2c form, which needs a v_mov to clear its register
+__device__ __forceinline__ int sdot2_first(s2 u, s2 h)
+{
+    int r;
+    asm("v_dot2_i32_i16 %0, %1, %2, 0" : "=v"(r) : "v"(u), "v"(h));
+    return r;
+}
+
+// w = M h for the staged link forms of M (U or U^+): words 2e, 2e + 1 of
+// entry e = 3a + b hold the pairs whose dot products with h_b give the real
+// and imaginary parts of M_ab h_b
+__device__ __forceinline__ void link_mul_i16(const unsigned L[18], const s2 h[6], cx<float> w[6])
+{
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int re = sdot2_first(as_s2(L[6 * a]), h[3 * sp]);
+            int im = sdot2_first(as_s2(L[6 * a + 1]), h[3 * sp]);
+#pragma unroll
+            for (int b = 1; b < 3; ++b) {
+                re = __builtin_amdgcn_sdot2(as_s2(L[6 * a + 2 * b]), h[3 * sp + b], re, false);
+                im = __builtin_amdgcn_sdot2(as_s2(L[6 * a + 2 * b + 1]), h[3 * sp + b], im, false);
+            }
+            w[3 * sp + a] = cx<float>{(float)re, (float)im};
+        }
+}
+
 // Where the stencil reads its input spinor field and links from: plain
 // pointers (FP64 fields, any lane layout) or per-wave buffer views (scalar
 // resources) of a field stored in format S.  spinor() returns the site's
 // values up to a common factor, which it returns.
 template <typename R, class LK>
 struct PtrSrc {
+    static constexpr bool PACKED_I16 = false;
     static constexpr R LINK_UNIT = LK::UNIT;
     const typename SpinorFmt<R>::V *in;
     const typename LK::V *gauge;
@@ -141,6 +212,7 @@ struct PtrSrc {
 template <typename S, class LK>
 struct BufSrc {
     typedef typename SpinorFmt<S>::R R;
+    static constexpr bool PACKED_I16 = false;
     static constexpr R LINK_UNIT = LK::UNIT;
     Buf in, gauge;
     int Vh;
@@ -160,19 +232,37 @@ __device__ __forceinline__ void hop_dir(int p, int i, int nf, int nb, R sf, R sb
 {
     constexpr int SF = DAG ? 1 : -1;
     constexpr int SB = DAG ? -1 : 1;
-    cx<R> psi[12], h[6], w[6], U[3][3];
-    // forward hop: U_mu(x) psi(x + mu), link stored with the output parity
-    const R cf = src.template spinor<MU>(nf, psi);
-    project<MU, SF>(psi, h);
-    src.link(MU, p, i, U);
-    link_mul(U, h, w);
-    accumulate_scaled<MU, SF>(acc, w, sf * cf * SRC::LINK_UNIT);
-    // backward hop: U_mu(x - mu)^+ psi(x - mu), link stored at the neighbour
-    const R cb = src.template spinor<MU>(nb, psi);
-    project<MU, SB>(psi, h);
-    src.link(MU, 1 - p, nb, U);
-    link_adj_mul(U, h, w);
-    accumulate_scaled<MU, SB>(acc, w, sb * cb * SRC::LINK_UNIT);
+    if constexpr (SRC::PACKED_I16) {
+        // spinor_i16 returns the halved integers and the factor that turns
+        // them (times the staged link integers) into values
+        s2 psi[12], h[6];
+        unsigned L[18];
+        cx<float> w[6];
+        const float cf = src.template spinor_i16<MU>(nf, psi);
+        project_i16<MU, SF>(psi, h);
+        src.link_i16(2 * MU, L);
+        link_mul_i16(L, h, w);
+        accumulate_scaled<MU, SF>(acc, w, sf * cf);
+        const float cb = src.template spinor_i16<MU>(nb, psi);
+        project_i16<MU, SB>(psi, h);
+        src.link_i16(2 * MU + 1, L);
+        link_mul_i16(L, h, w);
+        accumulate_scaled<MU, SB>(acc, w, sb * cb);
+    } else {
+        cx<R> psi[12], h[6], w[6], U[3][3];
+        // forward hop: U_mu(x) psi(x + mu), link stored with the output parity
+        const R cf = src.template spinor<MU>(nf, psi);
+        project<MU, SF>(psi, h);
+        src.link(MU, p, i, U);
+        link_mul(U, h, w);
+        accumulate_scaled<MU, SF>(acc, w, sf * cf * SRC::LINK_UNIT);
+        // backward hop: U_mu(x - mu)^+ psi(x - mu), link stored at the neighbour
+        const R cb = src.template spinor<MU>(nb, psi);
+        project<MU, SB>(psi, h);
+        src.link(MU, 1 - p, nb, U);
+        link_adj_mul(U, h, w);
+        accumulate_scaled<MU, SB>(acc, w, sb * cb * SRC::LINK_UNIT);
+    }
 }
 
 template <bool DAG, typename R, class SRC>
