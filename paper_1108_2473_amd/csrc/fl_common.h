@@ -345,10 +345,12 @@ struct SpinorFmt<float> {
 
 // 16-bit fixed-point spinor storage with one FP32 scale per site: the 24
 // reals of a site are divided by their largest magnitude m and stored as
-// round(32767 v / m) in int16 (three 16-byte vectors, complex entry 4c + w in
-// word w of vector c, real part in the low half); the scale m / 32767 follows
+// round(16383 v / m) in int16 (three 16-byte vectors, complex entry 4c + w in
+// word w of vector c, real part in the low half); the scale m / 16383 follows
 // the three vector arrays as an FP32 array.  Relative rounding error per
-// component <= 1 / 65534 of the site's largest component.
+// component <= 1 / 32766 of the site's largest component.  The 15-bit range
+// leaves room for the sum or difference of two stored values in int16, which
+// the packed hop uses for its spin projection.
 struct H16 {};
 
 __device__ __forceinline__ cx<float> h16_pair(unsigned w)
@@ -368,18 +370,6 @@ typedef short s2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ s2 as_s2(unsigned w) { return __builtin_bit_cast(s2, w); }
 __device__ __forceinline__ s2 swp(s2 z) { return __builtin_shufflevector(z, z, 1, 0); }
-
-// the 12 stored words of a site, each int16 halved (arithmetic shift)
-__device__ __forceinline__ void h16_halve(const v4u u[3], s2 p[12])
-{
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        p[4 * c] = as_s2(u[c].x) >> (s2){1, 1};
-        p[4 * c + 1] = as_s2(u[c].y) >> (s2){1, 1};
-        p[4 * c + 2] = as_s2(u[c].z) >> (s2){1, 1};
-        p[4 * c + 3] = as_s2(u[c].w) >> (s2){1, 1};
-    }
-}
 
 template <>
 struct SpinorFmt<H16> {
@@ -420,8 +410,9 @@ struct SpinorFmt<H16> {
         float m = 0.0f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s[k].re), fabsf(s[k].im)));
-        const float inv = m > 0.0f ? 1.0f / m : 0.0f;
-        const float sc = m * (1.0f / 32767.0f);
+        // h16_pack(x) = round(32767 x): x = v / m * (16383 / 32767)
+        const float inv = m > 0.0f ? (16383.0f / 32767.0f) / m : 0.0f;
+        const float sc = m * (1.0f / 16383.0f);
         unsigned w[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
@@ -460,31 +451,19 @@ struct SpinorFmt<H16> {
         unpack(v, s);
         return ((const float *)(w + (size_t)3 * 16 * wsmax))[j];
     }
-    // integer forms for the packed hop: the stored integers halved, and the
-    // site's scale (a value is 2 * scale * halved integer, up to the
-    // rounding of the halving)
-    __device__ static __forceinline__ float load_half(const Buf &b, int Vh, int i, s2 p[12])
+    // integer form for the packed hop: the stored words of site i (one
+    // complex entry each) and the site's scale
+    __device__ static __forceinline__ float load_i16(const Buf &b, int Vh, int i, s2 p[12])
     {
-        v4u u[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) u[c] = __builtin_bit_cast(v4u, buf_ld16(b, i * 16, c * Vh * 16));
-        const float sc = buf_ld4(b, i * 4, 3 * Vh * 16);
-        h16_halve(u, p);
-        return sc;
-    }
-    // LDS window of halved integers, laid out as to_lds()
-    __device__ static __forceinline__ void to_lds_half(const Buf &b, int Vh, int i, unsigned char *w, int wsmax,
-                                                       int j)
-    {
-        s2 p[12];
-        const float sc = load_half(b, Vh, i, p);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            ((v4u *)w)[c * wsmax + j] = v4u{__builtin_bit_cast(unsigned, p[4 * c]),
-                                            __builtin_bit_cast(unsigned, p[4 * c + 1]),
-                                            __builtin_bit_cast(unsigned, p[4 * c + 2]),
-                                            __builtin_bit_cast(unsigned, p[4 * c + 3])};
-        ((float *)(w + (size_t)3 * 16 * wsmax))[j] = sc;
+        for (int c = 0; c < 3; ++c) {
+            const v4u u = __builtin_bit_cast(v4u, buf_ld16(b, i * 16, c * Vh * 16));
+            p[4 * c] = as_s2(u.x);
+            p[4 * c + 1] = as_s2(u.y);
+            p[4 * c + 2] = as_s2(u.z);
+            p[4 * c + 3] = as_s2(u.w);
+        }
+        return buf_ld4(b, i * 4, 3 * Vh * 16);
     }
     __device__ static __forceinline__ float lds_load_i16(const unsigned char *w, int wsmax, int j, s2 p[12])
     {
@@ -744,7 +723,8 @@ struct LinkQ16R12 {
     // in words 2e, 2e + 1 of entry e = 3a + b of the matrix applied
     static constexpr float HALF_UNIT = 2.0f / 32767.0f;
     static constexpr int PK_SNC = 18;
-    __device__ static __forceinline__ void stage_pk(const V v[NC], bool adj, SV w[PK_SNC])
+    template <bool ADJ>
+    __device__ static __forceinline__ void stage_pk(const V v[NC], SV w[PK_SNC])
     {
         cx<float> U[3][3];
         unpack(v, U);
@@ -753,11 +733,11 @@ struct LinkQ16R12 {
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                const cx<float> u = adj ? U[b][a] : U[a][b];
+                const cx<float> u = ADJ ? U[b][a] : U[a][b];
                 const float ur = u.re * k, ui = u.im * k;
                 const int e = 3 * a + b;
-                w[2 * e] = adj ? h16_pack(ur, ui) : h16_pack(ur, -ui);
-                w[2 * e + 1] = adj ? h16_pack(-ui, ur) : h16_pack(ui, ur);
+                w[2 * e] = ADJ ? h16_pack(ur, ui) : h16_pack(ur, -ui);
+                w[2 * e + 1] = ADJ ? h16_pack(-ui, ur) : h16_pack(ui, ur);
             }
     }
 };

@@ -140,11 +140,11 @@ struct LdsSrc {
     }
 };
 
-// Source of the packed integer hop (16-bit fields, lds mode 3): x/y
-// neighbours from the wave's LDS window of halved integers, z/t neighbours
-// from memory (halved on load), links from the workgroup's half-scale
-// staging.  The factor returned with a site's integers is its scale times 2
-// (the halving) times the staged link unit.
+// Source of the packed integer hop (16-bit fields, lds modes 3 and 4): x/y
+// neighbours from the wave's LDS window (mode 3) or from memory like the
+// z/t neighbours (mode 4), links from the workgroup's half-scale staging.
+// The factor returned with a site's integers is its scale times the staged
+// link unit.
 template <bool WIN>
 struct LdsSrcQ16 {
     static constexpr bool PACKED_I16 = true;
@@ -155,11 +155,11 @@ struct LdsSrcQ16 {
     template <int MU>
     __device__ __forceinline__ float spinor_i16(int i, s2 p[12]) const
     {
-        constexpr float k = 2.0f * LinkQ16R12::HALF_UNIT;
+        constexpr float k = LinkQ16R12::HALF_UNIT;
         if (WIN && MU < 2)
             return k * SpinorFmt<H16>::lds_load_i16(win, wsmax, i - wlo, p);
         else
-            return k * SpinorFmt<H16>::load_half(in, Vh, i, p);
+            return k * SpinorFmt<H16>::load_i16(in, Vh, i, p);
     }
     __device__ __forceinline__ void link_i16(int dslot, unsigned L[18]) const
     {
@@ -187,7 +187,7 @@ __device__ __forceinline__ int back_neighbour(const LatGeom &g, const Coord &c, 
 }
 
 // SLINK: links staged in LDS; PK (16-bit fields only, with SLINK): the
-// packed integer hop on halved windows and half-scale staged links;
+// packed integer hop with half-scale staged links;
 // NOWIN: no neighbour windows (x/y neighbours from memory like z/t)
 template <typename S, class LK, bool DAG, int EPI, bool SLINK, bool PK = false, bool NOWIN = false>
 __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024) void k_dslash_lds(DslashArgs a)
@@ -219,7 +219,8 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
         // the 8 links (4 forward at the site, 4 backward at the neighbour) of
         // the block's 64 sites, shared by all its right-hand sides
         for (int k = threadIdx.x; k < 8 * FL_WAVE; k += blockDim.x) {
-            const int dslot = k / FL_WAVE, s = k % FL_WAVE, mu = dslot >> 1;
+            // one direction slot per wave (64 consecutive k)
+            const int dslot = __builtin_amdgcn_readfirstlane(k / FL_WAVE), s = k % FL_WAVE, mu = dslot >> 1;
             const int site = i0 + s;
             LV v[LK::NC];
             if (site < Vh) {
@@ -238,7 +239,10 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             }
             if constexpr (PK) {
                 LSV w[LK::PK_SNC];
-                LK::stage_pk(v, (dslot & 1) != 0, w);
+                if (dslot & 1)
+                    LK::template stage_pk<true>(v, w);
+                else
+                    LK::template stage_pk<false>(v, w);
 #pragma unroll
                 for (int cc = 0; cc < LK::PK_SNC; ++cc) lk[(dslot * LK::PK_SNC + cc) * FL_WAVE + s] = w[cc];
             } else {
@@ -251,10 +255,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
     }
     if (live && !NOWIN)
         for (int j = lane; j < wsz; j += FL_WAVE) {
-            if constexpr (PK)
-                SpinorFmt<S>::to_lds_half(ibuf, Vh, wlo + j, win, wsmax, j);
-            else
-                SpinorFmt<S>::to_lds(ibuf, Vh, wlo + j, win, wsmax, j);
+            SpinorFmt<S>::to_lds(ibuf, Vh, wlo + j, win, wsmax, j);
         }
     __syncthreads();
     if (!live) return;

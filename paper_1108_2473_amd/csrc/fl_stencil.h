@@ -121,10 +121,10 @@ __device__ __forceinline__ void link_adj_mul(const cx<R> U[3][3], const cx<R> h[
 // point: the spin projection runs as packed int16 adds on the stored
 // integers and the colour product as exact int16 dot products summed in
 // int32 (v_dot2_i32_i16), converted to FP32 once per product component.
-// The neighbour's integers are halved first (arithmetic shift), so that no
-// projected component leaves the int16 range (|u| + |l| <= 2 * 16384), and
-// the links are staged at half scale, round(16383.5 u), which keeps every
-// three-term sum of a product row below sqrt(6) * 32768 * 16384 < 2^31
+// The fields store at most 16383 in magnitude, so no projected component
+// leaves the int16 range (|u| + |l| <= 32766), and the links are staged at
+// half scale, round(16383.5 u), which keeps every three-term sum of a
+// product row below sqrt(6) * 32766 * 16384 < 2^31
 // (Cauchy-Schwarz over the 6 reals of a unit row of U or U^+ and the 6
 // reals of a projected colour vector).  Each staged entry carries the two
 // int16 pairs that give the real and the imaginary part of its product with
@@ -132,7 +132,7 @@ __device__ __forceinline__ void link_adj_mul(const cx<R> U[3][3], const cx<R> h[
 // of anything.  A complex number is one 32-bit word, real part in the low
 // half.
 // ---------------------------------------------------------------------------
-// the projection of project<MU, S> on halved integers; i z = swp(z) * (-1, 1)
+// the projection of project<MU, S> on the stored integers; i z = swp(z) * (-1, 1)
 template <int MU, int S>
 __device__ __forceinline__ void project_i16(const s2 p[12], s2 h[6])
 {
@@ -233,7 +233,7 @@ __device__ __forceinline__ void hop_dir(int p, int i, int nf, int nb, R sf, R sb
     constexpr int SF = DAG ? 1 : -1;
     constexpr int SB = DAG ? -1 : 1;
     if constexpr (SRC::PACKED_I16) {
-        // spinor_i16 returns the halved integers and the factor that turns
+        // spinor_i16 returns the stored integers and the factor that turns
         // them (times the staged link integers) into values
         s2 psi[12], h[6];
         unsigned L[18];

@@ -10,10 +10,9 @@ side, from the storage rounding of each format:
   FP32   1e-5   (vectors and links rounded to 2^-24, a few hundred flops)
   BF16   5e-3   (links rounded to 2^-9 relative; the hop part is about a
                  third of Dhat psi at kappa = 0.2)
-  16-bit 1e-3   (each stored vector rounded to 1/65534 of its site's largest
-                 component, the packed hop halves its input (one more unit
-                 of 1/32767) and stages the links at 1/32767 absolute: a few
-                 1e-4 per hop on the hop part)
+  16-bit 1e-3   (each stored vector rounded to 1/32766 of its site's largest
+                 component, links to 1/65534 absolute, staged for the packed
+                 hop at 1/32767: a few 1e-4 per hop on the hop part)
 A dropped or sign-flipped hop direction changes at least 1/8 of the hop
 part, about 4e-2 of Dhat psi, far above every tolerance.
 """
@@ -81,10 +80,10 @@ def test_schur_operator(F, dims, prec, reals, lds, dagger):
 
 
 def test_packed_hop_matches_float_hop(F):
-    """lds 3 (integer arithmetic on halved inputs, half-scale links) and lds 2
-    (FP32 arithmetic on the same 16-bit storage) differ only by the halving
-    and the link re-rounding: their difference is well inside the 16-bit
-    tolerance, and both sit closer to each other than to a wrong operator."""
+    """lds 3 (exact integer products with half-scale links) and lds 2 (FP32
+    arithmetic on the same 16-bit storage) differ only by the link re-rounding
+    and the rounding of FP32 products: their difference is well inside the
+    16-bit tolerance."""
     dims = (4, 4, 4, 8)
     lat, U = lattice(F, dims)
     psi = S.random_spinors(dims, 2, 78)
