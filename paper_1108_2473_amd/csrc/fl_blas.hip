@@ -55,7 +55,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, v);
 #pragma unroll
             for (int k = 0; k < 12; ++k) r[k] = cmsub(r[k], al, v[k]);
-            F::store(fbuf<S>(a.f[2][l], g, rhs), Vh, i, r);
+            store_result<S>(fbuf<S>(a.f[2][l], g, rhs), Vh, i, r);
         } else if (OP == OP_BICG_XR) {
             const SysState &st = a.st[T.sys];
             cx<R> al = cpx_of<R>(st.alpha), om = cpx_of<R>(st.omega);
@@ -70,8 +70,8 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
                 x[k] = cmad(cmad(x[k], al, p[k]), om, s[k]);
                 s[k] = cmsub(s[k], om, t[k]);  // new r
             }
-            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, x);
-            F::store(fbuf<S>(a.f[4][l], g, rhs), Vh, i, s);  // reductions of the stored values
+            store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, x);
+            store_result<S>(fbuf<S>(a.f[4][l], g, rhs), Vh, i, s);  // reductions of the stored values
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 cx<R> d = cjmul(r0[k], s[k]);
@@ -88,21 +88,21 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             F::load(fbuf<S>(a.f[2][l], g, rhs), Vh, i, v);
 #pragma unroll
             for (int k = 0; k < 12; ++k) p[k] = cmad(r[k], be, cmsub(p[k], om, v[k]));
-            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
+            store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
         } else if (OP == OP_HI_TO_LO) {
             cx<double> h[12];
             cx<R> lo[12], r0[12];
             F64::load(fbuf<double>(a.f[1][l], g, rhs), Vh, i, h);
 #pragma unroll
             for (int k = 0; k < 12; ++k) lo[k] = cx<R>{(R)h[k].re, (R)h[k].im};
-            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, lo);
+            store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, lo);
             if (a.flag) {
-                F::store(fbuf<S>(a.f[2][l], g, rhs), Vh, i, lo);
-                F::store(fbuf<S>(a.f[3][l], g, rhs), Vh, i, lo);
+                store_result<S>(fbuf<S>(a.f[2][l], g, rhs), Vh, i, lo);
+                store_result<S>(fbuf<S>(a.f[3][l], g, rhs), Vh, i, lo);
                 cx<R> z[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) z[k] = cx<R>{(R)0, (R)0};
-                F::store(fbuf<S>(a.f[4][l], g, rhs), Vh, i, z);
+                store_result<S>(fbuf<S>(a.f[4][l], g, rhs), Vh, i, z);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) r0[k] = lo[k];
             } else {
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             if (a.flag) {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) lo[k] = cx<R>{(R)0, (R)0};
-                F::store(fbuf<S>(a.f[1][l], g, rhs), Vh, i, lo);
+                store_result<S>(fbuf<S>(a.f[1][l], g, rhs), Vh, i, lo);
             }
         } else if (OP == OP_SUB_HI) {
             cx<double> u[12], w[12];
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             cx<R> z[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) z[k] = cx<R>{(R)0, (R)0};
-            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, z);
+            store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, z);
         } else if (OP == OP_CG_XR) {
             const R al = (R)a.st[T.sys].alpha[0];
             cx<R> x[12], r[12], p[12], q[12];
@@ -157,8 +157,8 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
                 x[k] = cx<R>{fma(al, p[k].re, x[k].re), fma(al, p[k].im, x[k].im)};
                 r[k] = cx<R>{fma(-al, q[k].re, r[k].re), fma(-al, q[k].im, r[k].im)};
             }
-            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, x);
-            F::store(fbuf<S>(a.f[1][l], g, rhs), Vh, i, r);
+            store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, x);
+            store_result<S>(fbuf<S>(a.f[1][l], g, rhs), Vh, i, r);
 #pragma unroll
             for (int k = 0; k < 12; ++k) q2 += r[k].re * r[k].re + r[k].im * r[k].im;
         } else if (OP == OP_CG_P) {
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, z);
 #pragma unroll
             for (int k = 0; k < 12; ++k) p[k] = cx<R>{fma(be, p[k].re, z[k].re), fma(be, p[k].im, z[k].im)};
-            F::store(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
+            store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
         }
     }
     if (OP == OP_BICG_XR || OP == OP_HI_TO_LO || OP == OP_NORM || OP == OP_CG_XR) {

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define FL_MAXLAT 4
 #define FL_WAVE 64
 
@@ -122,9 +124,14 @@ __device__ __forceinline__ v2f buf_ld8(const Buf &b, int voff, int soff)
     return __builtin_amdgcn_raw_buffer_load_b64(b.r, voff, soff, 0);
 }
 
+// CP: cache policy of the store (0: default; ST_STREAM: non-temporal, for
+// results no later access of the same kernel reads)
+enum { ST_STREAM = 2 };
+
+template <int CP = 0>
 __device__ __forceinline__ void buf_st16(const Buf &b, v4f v, int voff, int soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b128(v, b.r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, b.r, voff, soff, CP);
 }
 
 // Store groups.  Measured on gfx950: a vector instruction issued shortly
@@ -176,9 +183,10 @@ __device__ __forceinline__ float buf_ld4(const Buf &b, int voff, int soff)
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, voff, soff, 0));
 }
 
+template <int CP = 0>
 __device__ __forceinline__ void buf_st4(const Buf &b, float v, int voff, int soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, voff, soff, CP);
 }
 
 __device__ __forceinline__ double2 v4f_to_d2(v4f v)
@@ -405,6 +413,7 @@ struct SpinorFmt<H16> {
         for (int k = 0; k < 12; ++k) s[k] = cx<float>{s[k].re * sc, s[k].im * sc};
     }
     // stores s and replaces it by the stored (rounded) values
+    template <int CP = 0>
     __device__ static __forceinline__ void store(const Buf &b, int Vh, int i, cx<float> s[12])
     {
         float m = 0.0f;
@@ -433,8 +442,8 @@ struct SpinorFmt<H16> {
         asm volatile("" : "+v"(vo16), "+v"(vo4), "+v"(scv));
         store_fence_begin();
 #pragma unroll
-        for (int c = 0; c < 3; ++c) buf_st16(b, v[c], vo16, c * Vh * 16);
-        buf_st4(b, scv, vo4, 3 * Vh * 16);
+        for (int c = 0; c < 3; ++c) buf_st16<CP>(b, v[c], vo16, c * Vh * 16);
+        buf_st4<CP>(b, scv, vo4, 3 * Vh * 16);
         store_drain();
     }
     __device__ static __forceinline__ void to_lds(const Buf &b, int Vh, int i, unsigned char *w, int wsmax, int j)
@@ -478,6 +487,18 @@ struct SpinorFmt<H16> {
         return ((const float *)(w + (size_t)3 * 16 * wsmax))[j];
     }
 };
+
+// store of a kernel's result that no later access of the same kernel reads:
+// non-temporal for 16-bit fields, so that it does not evict the inputs that
+// neighbouring workgroups still read from L2
+template <typename S>
+__device__ __forceinline__ void store_result(const Buf &b, int Vh, int i, cx<typename SpinorFmt<S>::R> s[12])
+{
+    if constexpr (std::is_same<S, H16>::value)
+        SpinorFmt<S>::template store<ST_STREAM>(b, Vh, i, s);
+    else
+        SpinorFmt<S>::store(b, Vh, i, s);
+}
 
 // per-wave buffer view of right-hand side `rhs` of a field in format S
 template <typename S>

@@ -50,7 +50,7 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
 #pragma unroll
         for (int k = 0; k < 12; ++k) out[k] = cb * acc[k];
     }
-    F::store(spinor_buf<S>(a.out[T.lat], g.Vh, rhs), g.Vh, T.site, out);
+    store_result<S>(spinor_buf<S>(a.out[T.lat], g.Vh, rhs), g.Vh, T.site, out);
     if (EPI & EPI_DOTX_NORM) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
