@@ -39,7 +39,12 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
     typedef typename SpinorFmt<S>::R R;
     TileInfo T = tile_info(a.B);
     if (!T.valid_rhs) return;
-    if (a.mask && !a.mask[T.sys]) return;
+    if (OP == OP_CG_PX) {
+        // a system that stopped in this iteration still owes its x update
+        if (!a.mask[T.sys] && a.st[T.sys].xstamp != a.stamp) return;
+    } else if (a.mask && !a.mask[T.sys]) {
+        return;
+    }
     const LatGeom &g = a.B.lat[T.lat];
     const int l = T.lat, i = T.site, Vh = g.Vh;
     const int rhs = __builtin_amdgcn_readfirstlane(T.rhs);
@@ -145,20 +150,14 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
 #pragma unroll
             for (int k = 0; k < 12; ++k) z[k] = cx<R>{(R)0, (R)0};
             store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, z);
-        } else if (OP == OP_CG_XR) {
+        } else if (OP == OP_CG_R) {
             const R al = (R)a.st[T.sys].alpha[0];
-            cx<R> x[12], r[12], p[12], q[12];
-            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, x);
-            F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, r);
-            F::load(fbuf<S>(a.f[2][l], g, rhs), Vh, i, p);
-            F::load(fbuf<S>(a.f[3][l], g, rhs), Vh, i, q);
+            cx<R> r[12], q[12];
+            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, r);
+            F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, q);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                x[k] = cx<R>{fma(al, p[k].re, x[k].re), fma(al, p[k].im, x[k].im)};
-                r[k] = cx<R>{fma(-al, q[k].re, r[k].re), fma(-al, q[k].im, r[k].im)};
-            }
-            store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, x);
-            store_result<S>(fbuf<S>(a.f[1][l], g, rhs), Vh, i, r);
+            for (int k = 0; k < 12; ++k) r[k] = cx<R>{fma(-al, q[k].re, r[k].re), fma(-al, q[k].im, r[k].im)};
+            store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, r);
 #pragma unroll
             for (int k = 0; k < 12; ++k) q2 += r[k].re * r[k].re + r[k].im * r[k].im;
         } else if (OP == OP_CG_P) {
@@ -169,9 +168,31 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
 #pragma unroll
             for (int k = 0; k < 12; ++k) p[k] = cx<R>{fma(be, p[k].re, z[k].re), fma(be, p[k].im, z[k].im)};
             store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
+        } else if (OP == OP_CG_PX) {
+            // wave-uniform: one wave is one system
+            const SysState &st = a.st[T.sys];
+            const bool xu = st.xstamp == a.stamp, pu = a.mask[T.sys] != 0;
+            cx<R> p[12];
+            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
+            if (xu) {
+                const R al = (R)st.alpha[0];
+                cx<R> x[12];
+                F::load(fbuf<S>(a.f[2][l], g, rhs), Vh, i, x);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) x[k] = cx<R>{fma(al, p[k].re, x[k].re), fma(al, p[k].im, x[k].im)};
+                store_result<S>(fbuf<S>(a.f[2][l], g, rhs), Vh, i, x);
+            }
+            if (pu) {
+                const R be = (R)st.beta[0];
+                cx<R> z[12];
+                F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, z);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) p[k] = cx<R>{fma(be, p[k].re, z[k].re), fma(be, p[k].im, z[k].im)};
+                store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
+            }
         }
     }
-    if (OP == OP_BICG_XR || OP == OP_HI_TO_LO || OP == OP_NORM || OP == OP_CG_XR) {
+    if (OP == OP_BICG_XR || OP == OP_HI_TO_LO || OP == OP_NORM || OP == OP_CG_R) {
         double s0 = wave_sum((double)q0), s1 = wave_sum((double)q1), s2 = wave_sum((double)q2);
         constexpr int which = (OP == OP_BICG_XR || OP == OP_HI_TO_LO) ? 7 : 4;
         write_partials(a.partial, a.slot0, a.nsys, T.sys, a.B.nsb_max, T.sb, s0, s1, s2, which);
@@ -190,8 +211,9 @@ void dispatch(const BlasArgs &a, dim3 grid, dim3 block, hipStream_t s)
     case OP_SUB_HI: hipLaunchKernelGGL((k_blas<S, OP_SUB_HI>), grid, block, 0, s, a); break;
     case OP_NORM: hipLaunchKernelGGL((k_blas<S, OP_NORM>), grid, block, 0, s, a); break;
     case OP_ZERO: hipLaunchKernelGGL((k_blas<S, OP_ZERO>), grid, block, 0, s, a); break;
-    case OP_CG_XR: hipLaunchKernelGGL((k_blas<S, OP_CG_XR>), grid, block, 0, s, a); break;
+    case OP_CG_R: hipLaunchKernelGGL((k_blas<S, OP_CG_R>), grid, block, 0, s, a); break;
     case OP_CG_P: hipLaunchKernelGGL((k_blas<S, OP_CG_P>), grid, block, 0, s, a); break;
+    case OP_CG_PX: hipLaunchKernelGGL((k_blas<S, OP_CG_PX>), grid, block, 0, s, a); break;
     default: break;
     }
 }
@@ -315,6 +337,7 @@ __device__ __forceinline__ void scal_step(const ScalArgs &a, const double P[6], 
         break;
     case SC_CG_BETA: {  // slot 2: |z'|^2, slot 5: |r|^2
         double zn = P[2], rr = P[5];
+        s.xstamp = a.stamp;  // r moved by alpha q in this iteration: x moves by alpha p
         s.iter += 1;
         s.rr = rr;
         if (!finite_d(zn) || !finite_d(rr)) {

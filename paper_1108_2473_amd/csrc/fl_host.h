@@ -75,7 +75,7 @@ struct SysState {
     double zz;      // CGNR: |z|^2
     int iter, max_iter;
     int flags;
-    int pad;
+    int xstamp;  // CGNR: iteration stamp whose x update (x += alpha p) is still to be applied
 };
 
 enum {
@@ -94,8 +94,10 @@ enum BlasOp {
     OP_SUB_HI,        // f0 out (FP64) = f1 - f2 (FP64)
     OP_NORM,          // |f0|^2 -> slot0+2
     OP_ZERO,          // f0 = 0
-    OP_CG_XR,         // CGNR: f0 x += a p; f1 r -= a q (f2 p, f3 q); real a = zz/qq
-    OP_CG_P           // CGNR: f0 p = f1 z + beta p
+    OP_CG_R,          // CGNR: f0 r -= a q (f1 q), |r|^2; real a = zz/qq
+    OP_CG_P,          // CGNR: f0 p = f1 z + beta p
+    OP_CG_PX          // CGNR: f2 x += a p where the state carries this launch's stamp, then
+                      //       f0 p = f1 z + beta p for the masked (active) systems
 };
 
 struct BlasArgs {
@@ -107,6 +109,7 @@ struct BlasArgs {
     const int *mask;
     double *partial;
     SysState *st;
+    int stamp;  // iteration stamp (OP_CG_PX)
     void *f[6][FL_MAXLAT];
 };
 
@@ -124,6 +127,7 @@ struct ScalArgs {
     const int *mask;  // systems to process (null: all active)
     const double *partial;
     SysState *st;
+    int stamp;  // iteration stamp, recorded by SC_CG_BETA
 };
 void launch_scalars(const ScalArgs &a, hipStream_t s);
 

@@ -44,6 +44,7 @@ struct Solver {
     double kap2[FL_MAXLAT];
     double *partial = nullptr;
     SysState *dst = nullptr;
+    int stamp = 0;  // CGNR iteration stamp
     int *active = nullptr, *mask = nullptr;
     std::vector<SysState> hst;
     std::vector<int> hact, hmask;
@@ -91,6 +92,7 @@ struct Solver {
         a.mask = msk;
         a.partial = partial;
         a.st = dst;
+        a.stamp = stamp;
         int k = 0;
         for (const MF *f : fields) {
             for (int l = 0; l < B.nlat; ++l) a.f[k][l] = f->p[l];
@@ -109,6 +111,7 @@ struct Solver {
         a.mask = msk;
         a.partial = partial;
         a.st = dst;
+        a.stamp = stamp;
         launch_scalars(a, st);
     }
 
@@ -139,16 +142,18 @@ struct Solver {
     void cg_iteration()
     {
         const VecFormat lf = vf;
+        ++stamp;
         // q = Dhat p with |q|^2 (slot 2)
         dslash(fmt, true, 1, P, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, false, true);
         dslash(fmt, true, 0, TMP, V, &P, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, false, false);
         scal(SC_CG_ALPHA, nullptr);
-        blas(lf, OP_CG_XR, {&XL, &R, &P, &V}, 0, 3, active);      // |r|^2 -> slot 5
+        blas(lf, OP_CG_R, {&R, &V}, 0, 3, active);                // r -= alpha q, |r|^2 -> slot 5
         // z = Dhat^+ r with |z|^2 (slot 2)
         dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, true, false);
         dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, true, false);
         scal(SC_CG_BETA, nullptr);
-        blas(lf, OP_CG_P, {&P, &S}, 0, 0, active);
+        // x += alpha p (also for a system that stopped in SC_CG_BETA), then p = z + beta p
+        blas(lf, OP_CG_PX, {&P, &S, &XL}, 0, 0, active);
     }
 
     // FP64 residual of the masked systems: rh = bh - Dhat xh (|rh|^2 -> slot 2),
