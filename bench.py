@@ -254,14 +254,12 @@ def main():
     Vh = S.volume(dims) // 2
     pairs = (bytes_per_launch - 8 * LINK_BYTES[args.prec] * Vh) / (2 * SITE_BYTES[args.prec])
     tflops = FLOP_PER_SITE * pairs / (avg_us * 1e-6) / 1e12 if avg_us > 0 else 0.0
-    if args.prec == "h16":
-        # the 16-bit kernel is bound by vector-instruction issue, not by HBM
-        roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
-                "hbm_algorithmic_GBs": round(achieved, 1)}
-    else:
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "fp32_TFLOPs": round(tflops, 2)}
+    # every storage format's hopping kernel is limited by the memory system
+    # (for 16-bit storage its HBM-side traffic runs at ~83 % of the plain-copy
+    # rate with the vector units ~2/3 busy); the FP32 rate is reported beside it
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "fp32_TFLOPs": round(tflops, 2),
+            "fp32_frac": round(tflops / FP32_PEAK_TFLOPS, 4)}
     out = {
         "metric": METRIC,
         "value": round(value, 3),

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, lo);
 #pragma unroll
             for (int k = 0; k < 12; ++k) h[k] = h[k] + cx<double>{(double)lo[k].re, (double)lo[k].im};
-            F64::store(fbuf<double>(a.f[0][l], g, rhs), Vh, i, h);
+            store_result<double>(fbuf<double>(a.f[0][l], g, rhs), Vh, i, h);
             if (a.flag) {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) lo[k] = cx<R>{(R)0, (R)0};
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             F64::load(fbuf<double>(a.f[2][l], g, rhs), Vh, i, w);
 #pragma unroll
             for (int k = 0; k < 12; ++k) u[k] = u[k] - w[k];
-            F64::store(fbuf<double>(a.f[0][l], g, rhs), Vh, i, u);
+            store_result<double>(fbuf<double>(a.f[0][l], g, rhs), Vh, i, u);
         } else if (OP == OP_NORM) {
             cx<R> f[12];
             F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, f);

@@ -159,12 +159,12 @@ __device__ __forceinline__ void buf_st8(const Buf &b, v2f v, int voff, int soff)
 
 // N 16-byte vectors of one lane at byte offsets voff + c * cstride (cstride
 // wave-uniform), as one store group
-template <int N>
+template <int N, int CP = 0>
 __device__ __forceinline__ void st16_group(const Buf &b, const v4f (&v)[N], int voff, int cstride)
 {
     store_fence_begin();
 #pragma unroll
-    for (int c = 0; c < N; ++c) buf_st16(b, v[c], voff, c * cstride);
+    for (int c = 0; c < N; ++c) buf_st16<CP>(b, v[c], voff, c * cstride);
     store_drain();
 }
 
@@ -259,12 +259,13 @@ struct SpinorFmt<double> {
             s[c] = cx<double>{v.x, v.y};
         }
     }
+    template <int CP = 0>
     __device__ static __forceinline__ void store(const Buf &b, int Vh, int i, const cx<double> s[12])
     {
         v4f v[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = d2_to_v4f(make_double2(s[c].re, s[c].im));
-        st16_group(b, v, i * 16, Vh * 16);
+        st16_group<12, CP>(b, v, i * 16, Vh * 16);
     }
     __device__ static __forceinline__ double load_raw(const Buf &b, int Vh, int i, cx<double> s[12])
     {
@@ -322,12 +323,13 @@ struct SpinorFmt<float> {
             s[2 * c + 1] = cx<float>{v.z, v.w};
         }
     }
+    template <int CP = 0>
     __device__ static __forceinline__ void store(const Buf &b, int Vh, int i, const cx<float> s[12])
     {
         v4f v[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[c] = v4f{s[2 * c].re, s[2 * c].im, s[2 * c + 1].re, s[2 * c + 1].im};
-        st16_group(b, v, i * 16, Vh * 16);
+        st16_group<6, CP>(b, v, i * 16, Vh * 16);
     }
     __device__ static __forceinline__ float load_raw(const Buf &b, int Vh, int i, cx<float> s[12])
     {
@@ -489,15 +491,12 @@ struct SpinorFmt<H16> {
 };
 
 // store of a kernel's result that no later access of the same kernel reads:
-// non-temporal for 16-bit fields, so that it does not evict the inputs that
-// neighbouring workgroups still read from L2
+// non-temporal, so that it does not evict the inputs that neighbouring
+// workgroups still read from L2
 template <typename S>
 __device__ __forceinline__ void store_result(const Buf &b, int Vh, int i, cx<typename SpinorFmt<S>::R> s[12])
 {
-    if constexpr (std::is_same<S, H16>::value)
-        SpinorFmt<S>::template store<ST_STREAM>(b, Vh, i, s);
-    else
-        SpinorFmt<S>::store(b, Vh, i, s);
+    SpinorFmt<S>::template store<ST_STREAM>(b, Vh, i, s);
 }
 
 // per-wave buffer view of right-hand side `rhs` of a field in format S
