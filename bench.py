@@ -225,13 +225,16 @@ def main():
     cpu = None
     loop_err = None
     if not args.no_cpu_baseline:
+        # a bounded sample of the timed workload: two of its diluted sources
+        ncpu = 2
         t2 = time.perf_counter()
-        x_or, it_or, res_or, fails = O.solve(U, b[:1], dims, bc, kappa, tol=1e-12, max_iter=1200)
+        x_or, it_or, res_or, fails = O.solve(U, np.stack(srcs[:ncpu]), dims, bc, kappa, tol=1e-12, max_iter=1200)
         t_or = time.perf_counter() - t2
-        cpu = {"value": 1.0 / t_or, "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
-               "sample": f"one spin-colour-time diluted Z4 source of the same 16^3x32 workload solved "
-                         f"by the FP64 oracle (even-odd BiCGStab, {int(it_or[0])} iterations, "
-                         f"|Dx-b|/|b| = {res_or[0]:.1e}) in {t_or:.1f} s"}
+        cpu = {"value": ncpu / t_or, "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"{ncpu} spin-colour-time diluted Z4 sources of the same 16^3x32 workload (timeslices "
+                         f"0 and 5) solved by the FP64 oracle (even-odd BiCGStab, "
+                         f"{'/'.join(str(int(v)) for v in it_or[:ncpu])} iterations, |Dx-b|/|b| <= "
+                         f"{max(res_or[:ncpu]):.1e}) in {t_or:.1f} s"}
         # loop error vs FP64: this source's contribution eta^+ Gamma phi on its timeslice
         Vs = dims[0] * dims[1] * dims[2]
         e = b[0, :Vs]
@@ -245,7 +248,8 @@ def main():
                 l1 = np.abs(lo).max()
             errs.append(np.abs(lg - lo).max() / l1)
         loop_err = max(errs)
-        log(f"[bench] oracle {t_or:.1f}s ({O.num_threads()} threads); loop rel err vs FP64 {loop_err:.2e}")
+        log(f"[bench] oracle {t_or:.1f}s for {ncpu} solves ({O.num_threads()} threads); "
+            f"loop rel err vs FP64 {loop_err:.2e}")
 
     bytes_per_launch = prof["bytes"] / max(1, prof["launches"])
     traffic = profiled_traffic(args.prec)
