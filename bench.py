@@ -286,8 +286,9 @@ def main():
             "inner": f"{args.solver} on the even-odd Schur system, " + {
                 "f32": "fp32 vectors and 12-real links",
                 "bf16": "fp32 vectors, bf16 12-real links",
-                "h16": "16-bit fixed-point vectors (fp32 site scale) and 12-real links"}[args.prec]
-                     + ", fp32 arithmetic, fp64 reliable updates",
+                "h16": "16-bit fixed-point vectors (15-bit range, fp32 site scale) and 12-real links; hopping "
+                       "term as exact int16 products summed in int32 (v_dot2_i32_i16), accumulated in fp32"}[args.prec]
+                     + ", fp32 vector arithmetic, fp64 reliable updates",
             "batch": args.batch,
             "lds_mode": args.lds,
             "rt": args.rt,

@@ -150,6 +150,24 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
 #pragma unroll
             for (int k = 0; k < 12; ++k) z[k] = cx<R>{(R)0, (R)0};
             store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, z);
+        } else if (OP == OP_DOT) {
+            cx<R> u[12], w[12];
+            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, u);
+            F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, w);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                cx<R> d = cjmul(u[k], w[k]);
+                q0 += d.re;
+                q1 += d.im;
+            }
+        } else if (OP == OP_CG_FIXP) {
+            const cx<R> c = {(R)a.st[T.sys].beta[0], (R)a.st[T.sys].beta[1]};
+            cx<R> p[12], z[12];
+            F::load(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
+            F::load(fbuf<S>(a.f[1][l], g, rhs), Vh, i, z);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) p[k] = cmad(p[k], c, z[k]);
+            store_result<S>(fbuf<S>(a.f[0][l], g, rhs), Vh, i, p);
         } else if (OP == OP_CG_R) {
             const R al = (R)a.st[T.sys].alpha[0];
             cx<R> r[12], q[12];
@@ -192,9 +210,9 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             }
         }
     }
-    if (OP == OP_BICG_XR || OP == OP_HI_TO_LO || OP == OP_NORM || OP == OP_CG_R) {
+    if (OP == OP_BICG_XR || OP == OP_HI_TO_LO || OP == OP_NORM || OP == OP_CG_R || OP == OP_DOT) {
         double s0 = wave_sum((double)q0), s1 = wave_sum((double)q1), s2 = wave_sum((double)q2);
-        constexpr int which = (OP == OP_BICG_XR || OP == OP_HI_TO_LO) ? 7 : 4;
+        constexpr int which = (OP == OP_BICG_XR || OP == OP_HI_TO_LO) ? 7 : (OP == OP_DOT ? 3 : 4);
         write_partials(a.partial, a.slot0, a.nsys, T.sys, a.B.nsb_max, T.sb, s0, s1, s2, which);
     }
 }
@@ -214,6 +232,8 @@ void dispatch(const BlasArgs &a, dim3 grid, dim3 block, hipStream_t s)
     case OP_CG_R: hipLaunchKernelGGL((k_blas<S, OP_CG_R>), grid, block, 0, s, a); break;
     case OP_CG_P: hipLaunchKernelGGL((k_blas<S, OP_CG_P>), grid, block, 0, s, a); break;
     case OP_CG_PX: hipLaunchKernelGGL((k_blas<S, OP_CG_PX>), grid, block, 0, s, a); break;
+    case OP_DOT: hipLaunchKernelGGL((k_blas<S, OP_DOT>), grid, block, 0, s, a); break;
+    case OP_CG_FIXP: hipLaunchKernelGGL((k_blas<S, OP_CG_FIXP>), grid, block, 0, s, a); break;
     default: break;
     }
 }
@@ -358,16 +378,24 @@ __device__ __forceinline__ void scal_step(const ScalArgs &a, const double P[6], 
         }
         break;
     }
-    case SC_CG_REZ:  // after a residual replacement that keeps p: slot 2 |z|^2, z = Dhat^+ r; slot 5 |r|^2
+    case SC_CG_REZ: {  // after a residual replacement that keeps p: slot 2 |z|^2, z = Dhat^+ r;
+                       // slots 0, 1 <z, p>; slot 5 |r|^2
+        // CG's step length alpha = |z|^2 / |Dhat p|^2 assumes <z, p> = |z|^2,
+        // which holds for the iteration's own z but not for the replaced one;
+        // p += c z with c = (|z|^2 - <z, p>) / |z|^2 restores it
         s.zz = P[2];
         s.rr = P[5];
         s.rmax2 = P[5];
         s.flags &= ~(ST_CONV_ITER | ST_WANT_UPD);
+        const double zz = P[2] > 0 ? P[2] : 1.0;
+        s.beta[0] = (P[2] - P[0]) / zz;
+        s.beta[1] = -P[1] / zz;
         if (!(P[2] > 0) || !finite_d(P[2])) {
             s.flags |= ST_BREAK;
             act = 0;
         }
         break;
+    }
     default: break;
     }
 }

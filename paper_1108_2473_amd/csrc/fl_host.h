@@ -96,8 +96,10 @@ enum BlasOp {
     OP_ZERO,          // f0 = 0
     OP_CG_R,          // CGNR: f0 r -= a q (f1 q), |r|^2; real a = zz/qq
     OP_CG_P,          // CGNR: f0 p = f1 z + beta p
-    OP_CG_PX          // CGNR: f2 x += a p where the state carries this launch's stamp, then
+    OP_CG_PX,         // CGNR: f2 x += a p where the state carries this launch's stamp, then
                       //       f0 p = f1 z + beta p for the masked (active) systems
+    OP_DOT,           // <f0, f1> = sum conj(f0) f1 -> slots slot0, slot0 + 1
+    OP_CG_FIXP        // CGNR after a residual replacement: f0 p += c f1 z, complex c = beta[0..1]
 };
 
 struct BlasArgs {

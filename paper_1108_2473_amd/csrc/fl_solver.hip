@@ -314,10 +314,16 @@ fl_status Solver::run(std::vector<SysResult> &res)
     };
     auto cg_rez = [&](const int *msk) {
         // reliable update that keeps p: z = Dhat^+ r for the replaced r
-        // (|z|^2 -> slot 2, |r|^2 already in slot 5), new |z|^2 for alpha
+        // (|z|^2 -> slot 2, |r|^2 already in slot 5, <z, p> -> slots 0, 1),
+        // new |z|^2 for alpha, and p += c z so that <z, p> = |z|^2 again
+        // (without it, a replaced residual that has moved away from the
+        // recursive one, as it does when an iteration gains a lot between
+        // two host checks, derails the recurrence)
         dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, true, false);
         dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, msk, true, false);
+        blas(vf, OP_DOT, {&S, &P}, 0, 0, msk);
         scal(SC_CG_REZ, msk);
+        blas(vf, OP_CG_FIXP, {&P, &S}, 0, 0, msk);
     };
     if (solver == FL_SOLVER_CGNR) {
         cg_start(nullptr);
