@@ -93,6 +93,32 @@ def test_solve_meets_stopping_rule(F, name, prec, reals, solver):
     assert np.abs(x - xo).max() <= 1e-10 * np.abs(xo).max()
 
 
+@pytest.mark.parametrize("prec,solver", [(1, 0), (2, 0), (3, 0), (1, 1), (2, 1), (3, 1)])
+@pytest.mark.parametrize("src", ["point-even", "point-odd", "random"])
+def test_solve_fast_convergence_matrix(F, prec, solver, src):
+    """Every mixed-precision iteration (FP32, bf16 links, 16-bit storage;
+    BiCGStab and CGNR) on a lattice where one iteration gains ~3x (4^4,
+    kappa = 0.1), so that the iteration runs far ahead of the host's
+    replacement checks: sparse and dense sources meet the stopping rule on
+    the full operator, recomputed by the oracle."""
+    dims = (4, 4, 4, 4)
+    lat, U = make(F, dims, 0.3, 0.10, -1, 1000)
+    V = S.volume(dims)
+    if src == "random":
+        b = S.random_spinors(dims, 3, 51)
+    else:
+        site = 0 if src == "point-even" else 1
+        b = np.zeros((3, V, 4, 3), complex)
+        for k in range(3):
+            b[k, site, k, (2 * k) % 3] = 1.0
+    x, info = lat.solve(b, F.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, solver=solver))
+    assert all(i["converged"] for i in info), info
+    r = b - O.apply_D(U, x, dims, -1, 0.10)
+    rel = np.linalg.norm(r.reshape(3, -1), axis=1) / np.linalg.norm(b.reshape(3, -1), axis=1)
+    assert np.all(rel <= 1.05e-12), rel
+    assert max(i["iters"] for i in info) <= 80, info
+
+
 def test_solve_zero_and_point_sources(F):
     """A zero right-hand side gives x = 0 with no iterations; point sources on even
     and odd sites are solved through the Schur complement."""
@@ -108,14 +134,15 @@ def test_solve_zero_and_point_sources(F):
 
 
 @pytest.mark.parametrize("prec", [1, 3])
-def test_truncated_solve_stops_at_its_tolerance(F, prec):
+@pytest.mark.parametrize("solver", [0, 1])
+def test_truncated_solve_stops_at_its_tolerance(F, prec, solver):
     """LP solve (truncated): FP32 (or 16-bit storage) iteration stopped at
     |r| <= tol |b|, no FP64 step; the true residual of the full operator then
     confirms that the low-precision operator is D to well below tol."""
     dims = (4, 4, 4, 8)
     lat, U = make(F, dims, 0.5, 0.13, -1, 41)
     b = S.random_spinors(dims, 4, 42)
-    x, info = lat.solve(b, F.SolverParams(tol=1e-3, truncated=True, inner_prec=prec))
+    x, info = lat.solve(b, F.SolverParams(tol=1e-3, truncated=True, inner_prec=prec, solver=solver))
     r = b - O.apply_D(U, x, dims, -1, 0.13)
     rel = np.linalg.norm(r.reshape(4, -1), axis=1) / np.linalg.norm(b.reshape(4, -1), axis=1)
     assert np.all(rel <= 1.2e-3), rel
