@@ -381,6 +381,32 @@ typedef short s2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ s2 as_s2(unsigned w) { return __builtin_bit_cast(s2, w); }
 __device__ __forceinline__ s2 swp(s2 z) { return __builtin_shufflevector(z, z, 1, 0); }
 
+// u . h (the products summed exactly in int32) as the three-operand form with
+// an inline zero accumulator: the builtin with a zero accumulator becomes
+// the two-operand v_dot2c form, which needs a v_mov to clear its register
+__device__ __forceinline__ int sdot2_first(s2 u, s2 h)
+{
+    int r;
+    asm("v_dot2_i32_i16 %0, %1, %2, 0" : "=v"(r) : "v"(u), "v"(h));
+    return r;
+}
+
+// |v|^2 of a stored 16-bit site (words w, scale sc) from its integers: exact
+// int32 sums of squares over three groups of four words (each <= 8 * 16383^2
+// < 2^31), scaled once
+__device__ __forceinline__ float h16_norm2(const unsigned w[12], float sc)
+{
+    float t = 0.0f;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        int n = sdot2_first(as_s2(w[4 * g]), as_s2(w[4 * g]));
+#pragma unroll
+        for (int k = 1; k < 4; ++k) n = __builtin_amdgcn_sdot2(as_s2(w[4 * g + k]), as_s2(w[4 * g + k]), n, false);
+        t += (float)n;
+    }
+    return t * sc * sc;
+}
+
 template <>
 struct SpinorFmt<H16> {
     typedef float R;
@@ -414,9 +440,10 @@ struct SpinorFmt<H16> {
 #pragma unroll
         for (int k = 0; k < 12; ++k) s[k] = cx<float>{s[k].re * sc, s[k].im * sc};
     }
-    // stores s and replaces it by the stored (rounded) values
+    // stores s; returns the site scale and the stored words
     template <int CP = 0>
-    __device__ static __forceinline__ void store(const Buf &b, int Vh, int i, cx<float> s[12])
+    __device__ static __forceinline__ float store_words(const Buf &b, int Vh, int i, const cx<float> s[12],
+                                                        unsigned w[12])
     {
         float m = 0.0f;
 #pragma unroll
@@ -424,13 +451,8 @@ struct SpinorFmt<H16> {
         // h16_pack(x) = round(32767 x): x = v / m * (16383 / 32767)
         const float inv = m > 0.0f ? (16383.0f / 32767.0f) / m : 0.0f;
         const float sc = m * (1.0f / 16383.0f);
-        unsigned w[12];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            w[k] = h16_pack(s[k].re * inv, s[k].im * inv);
-            cx<float> q = h16_pair(w[k]);
-            s[k] = cx<float>{q.re * sc, q.im * sc};
-        }
+        for (int k = 0; k < 12; ++k) w[k] = h16_pack(s[k].re * inv, s[k].im * inv);
         v4f v[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -447,6 +469,19 @@ struct SpinorFmt<H16> {
         for (int c = 0; c < 3; ++c) buf_st16<CP>(b, v[c], vo16, c * Vh * 16);
         buf_st4<CP>(b, scv, vo4, 3 * Vh * 16);
         store_drain();
+        return sc;
+    }
+    // stores s and replaces it by the stored (rounded) values
+    template <int CP = 0>
+    __device__ static __forceinline__ void store(const Buf &b, int Vh, int i, cx<float> s[12])
+    {
+        unsigned w[12];
+        const float sc = store_words<CP>(b, Vh, i, s, w);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const cx<float> q = h16_pair(w[k]);
+            s[k] = cx<float>{q.re * sc, q.im * sc};
+        }
     }
     __device__ static __forceinline__ void to_lds(const Buf &b, int Vh, int i, unsigned char *w, int wsmax, int j)
     {

@@ -50,6 +50,15 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
 #pragma unroll
         for (int k = 0; k < 12; ++k) out[k] = cb * acc[k];
     }
+    if constexpr (std::is_same<S, H16>::value && !(EPI & (EPI_DOTX_NORM | EPI_DOTY))) {
+        // 16-bit result without dot products: stored as words, its norm
+        // summed from the stored integers (no decode back to FP32)
+        unsigned w[12];
+        const float sc = F::template store_words<ST_STREAM>(spinor_buf<S>(a.out[T.lat], g.Vh, rhs), g.Vh, T.site,
+                                                           out, w);
+        if (EPI & EPI_NORM) q2 += h16_norm2(w, sc);
+        return;
+    }
     store_result<S>(spinor_buf<S>(a.out[T.lat], g.Vh, rhs), g.Vh, T.site, out);
     if (EPI & EPI_DOTX_NORM) {
 #pragma unroll

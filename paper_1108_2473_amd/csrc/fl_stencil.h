@@ -156,16 +156,6 @@ __device__ __forceinline__ void project_i16(const s2 p[12], s2 h[6])
     }
 }
 
-// u . h (the products summed exactly in int32) as the three-operand form with
-// an inline zero accumulator: the builtin with a zero accumulator becomes
-// the two-operand v_dot2c form, which needs a v_mov to clear its register
-__device__ __forceinline__ int sdot2_first(s2 u, s2 h)
-{
-    int r;
-    asm("v_dot2_i32_i16 %0, %1, %2, 0" : "=v"(r) : "v"(u), "v"(h));
-    return r;
-}
-
 // w = M h for the staged link forms of M (U or U^+): words 2e, 2e + 1 of
 // entry e = 3a + b hold the pairs whose dot products with h_b give the real
 // and imaginary parts of M_ab h_b
