@@ -271,9 +271,12 @@ fl_status fl_bench_dslash(fl_ctx *ctx, int prec, int gauge_reals, int nrhs, int 
  * 0 none, 1 each wavefront's x/y neighbour window, 2 windows plus the
  * workgroup's links, 3 (FL_PREC_H16 only) as 2 with the hop computed on the
  * stored 16-bit integers (packed int16 spin projection, exact int16 dot
- * products for the colour product, links staged at half scale), -1 the
- * built-in choice (2 when it fits).  rt = 0 restores the built-in workgroup
- * size.  FL_ERR_ARG for out-of-range values or lds 3 with another precision. */
+ * products for the colour product, links staged at half scale in the two
+ * forms those products need), 4 (FL_PREC_H16 only) as 3 without neighbour
+ * windows, -1 the built-in choice (4 for FL_PREC_H16, 1 for FP64, 2
+ * otherwise, each falling back to a smaller mode when its LDS does not fit).
+ * rt = 0 restores the built-in workgroup size.  FL_ERR_ARG for out-of-range
+ * values or lds 3, 4 with another precision. */
 fl_status fl_set_tile(fl_ctx *ctx, int prec, int gauge_reals, int rt, int group, int lds);
 
 /* Autotuner: time the hopping kernel for nrhs right-hand sides over the
