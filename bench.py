@@ -97,6 +97,8 @@ def main():
                     help="LDS mode of the hopping kernel (-1: the library default; 3: packed 16-bit hop)")
     ap.add_argument("--rt", type=int, default=0, help="right-hand sides per workgroup (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the timings of the other workloads (exact loops, uneven TSM batch, gradient)")
     ap.add_argument("--fp64-rhs", type=int, default=4, help="single-RHS FP64 GPU solves for the reference rate")
     ap.add_argument("--timed-only", action="store_true",
                     help="run only the warmup and timed steps (for kernel profiles of the timed region)")
@@ -207,6 +209,70 @@ def main():
                           "hopping_kernel": {"launches": prof["launches"], "avg_launch_us": round(avg_us, 2),
                                              "achieved_GBs": round(achieved, 1)}}), flush=True)
         return
+    # the other workloads of the path, timed once each outside the timed region:
+    # exact loops of one whole timeslice, the uneven truncated-solver batch of
+    # three lattices, and the gradient of exact loops
+    extras = None
+    if not args.no_extras:
+        extras = {}
+        gx = [0, 15]
+        We = S.WORKLOADS["exact_8x8x8x16"]
+        le = fl.Lattice(We["dims"], We["bc_t"], device=0)
+        le.set_gauge(S.random_links(We["dims"], We["eps"], We["link_seed"]))
+        le.set_kappa(We["kappa"])
+        pe = fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, solver=solver, batch=768)
+        le.loops_exact([1], gam, pe)  # warm-up (one timeslice)
+        torch.cuda.synchronize()
+        t_e = time.perf_counter()
+        le.loops_exact([0], gam, pe)
+        torch.cuda.synchronize()
+        t_e = time.perf_counter() - t_e
+        ns = 12 * We["dims"][0] * We["dims"][1] * We["dims"][2]
+        extras["exact_loops_8x8x8x16_one_timeslice"] = {
+            "point_sources": ns, "seconds": round(t_e, 3), "solves_per_s": round(ns / t_e, 1),
+            "inner": f"{args.solver} {args.prec}, tol 1e-12", "gammas": len(gam)}
+        log(f"[bench] exact loops 8^3x16, one timeslice: {ns} solves in {t_e:.2f} s ({ns / t_e:.0f} solves/s)")
+        le.close()
+        names = ["tsm_8x8x8x8", "tsm_12x12x12x24", "tsm_16x16x16x32"]
+        lts = []
+        for nme in names:
+            Wt = S.WORKLOADS[nme]
+            lt = fl.Lattice(Wt["dims"], Wt["bc_t"], device=0)
+            lt.set_gauge(S.random_links(Wt["dims"], Wt["eps"], Wt["link_seed"]))
+            lt.set_kappa(Wt["kappa"])
+            lts.append((lt, Wt))
+        qs = [fl.NoiseParams(noise=fl.NOISE_CZ2, seed=Wt["noise_seed"], r0=0, n_lp=64, n_hp=4, dilution=0,
+                             t_begin=0, t_end=Wt["dims"][3]) for (_, Wt) in lts]
+        lp_t = fl.SolverParams(tol=1e-3, truncated=True)
+        hp_t = fl.SolverParams(tol=1e-12)
+        torch.cuda.synchronize()
+        t_t = time.perf_counter()
+        fl.loops_stochastic_multi([lt for (lt, _) in lts], qs, gam, lp_t, hp_t)
+        torch.cuda.synchronize()
+        t_t = time.perf_counter() - t_t
+        extras["uneven_tsm_batch_8^4_12^3x24_16^3x32"] = {
+            "lp_solves": 3 * 64, "hp_solves": 3 * 4, "lp_tol": 1e-3, "hp_tol": 1e-12, "seconds": round(t_t, 3)}
+        log(f"[bench] uneven TSM batch (3 lattices, 64 LP + 4 HP each): {t_t:.2f} s")
+        for (lt, _) in lts:
+            lt.close()
+        Wg = S.WORKLOADS["grad_12x12x12x24"]
+        lg = fl.Lattice(Wg["dims"], Wg["bc_t"], device=0)
+        lg.set_gauge(S.random_links(Wg["dims"], Wg["eps"], Wg["link_seed"]))
+        lg.set_kappa(Wg["kappa"])
+        Vsg = Wg["dims"][0] * Wg["dims"][1] * Wg["dims"][2]
+        wg = np.ones((len(gx), 1, Vsg), complex)
+        torch.cuda.synchronize()
+        t_g = time.perf_counter()
+        lg.loops_grad([0], gx, wg, fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, solver=solver,
+                                                   batch=768))
+        torch.cuda.synchronize()
+        t_g = time.perf_counter() - t_g
+        extras["gradient_12x12x12x24_one_timeslice"] = {
+            "point_sources": 12 * Vsg, "gammas": len(gx), "seconds": round(t_g, 3),
+            "inner": f"{args.solver} {args.prec}, tol 1e-12 (forward solves; adjoints by g5-hermiticity)"}
+        log(f"[bench] gradient 12^3x24, one timeslice ({12 * Vsg} sources): {t_g:.2f} s")
+        lg.close()
+
     # accuracy and the plain FP64 single-RHS reference on sources of the same workload
     import oracle as O
     xi = O.noise(O.NOISE_Z4, W["noise_seed"], 0, dims)
@@ -308,6 +374,7 @@ def main():
         "loop_rel_err_vs_fp64": loop_err,
         "iterations": {"fp64_single": info64[0]["iters"], "mixed": info_mp[0]["iters"]},
         "disconnected_correlator": corr,
+        "other_workloads": extras,
     }
     print(json.dumps(out), flush=True)
 
