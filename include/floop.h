@@ -273,7 +273,8 @@ fl_status fl_bench_dslash(fl_ctx *ctx, int prec, int gauge_reals, int nrhs, int 
  * stored 16-bit integers (packed int16 spin projection, exact int16 dot
  * products for the colour product, links staged at half scale in the two
  * forms those products need), 4 (FL_PREC_H16 only) as 3 without neighbour
- * windows, -1 the built-in choice (4 for FL_PREC_H16, 1 for FP64, 2
+ * windows, every neighbour spinor loaded two directions before its use,
+ * -1 the built-in choice (4 for FL_PREC_H16, 1 for FP64, 2
  * otherwise, each falling back to a smaller mode when its LDS does not fit).
  * rt = 0 restores the built-in workgroup size.  FL_ERR_ARG for out-of-range
  * values or lds 3, 4 with another precision. */

@@ -391,6 +391,18 @@ __device__ __forceinline__ int sdot2_first(s2 u, s2 h)
     return r;
 }
 
+// swp(l) * k + u as one packed multiply-add: op_sel feeds the high half of l
+// to the low lane and its low half to the high lane
+__device__ __forceinline__ s2 mad_swp(s2 l, s2 k, s2 u)
+{
+    unsigned r;
+    asm("v_pk_mad_i16 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[0,1,1]"
+        : "=v"(r)
+        : "v"(__builtin_bit_cast(unsigned, l)), "s"(__builtin_bit_cast(unsigned, k)),
+          "v"(__builtin_bit_cast(unsigned, u)));
+    return as_s2(r);
+}
+
 // |v|^2 of a stored 16-bit site (words w, scale sc) from its integers: exact
 // int32 sums of squares over three groups of four words (each <= 8 * 16383^2
 // < 2^31), scaled once
@@ -440,17 +452,19 @@ struct SpinorFmt<H16> {
 #pragma unroll
         for (int k = 0; k < 12; ++k) s[k] = cx<float>{s[k].re * sc, s[k].im * sc};
     }
-    // stores s; returns the site scale and the stored words
+    // stores f s; returns the site scale and the stored words (the factor
+    // f only enters the scale and the sign of the words: f s rounds to the
+    // same integers as s)
     template <int CP = 0>
     __device__ static __forceinline__ float store_words(const Buf &b, int Vh, int i, const cx<float> s[12],
-                                                        unsigned w[12])
+                                                        unsigned w[12], float f = 1.0f)
     {
         float m = 0.0f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(s[k].re), fabsf(s[k].im)));
         // h16_pack(x) = round(32767 x): x = v / m * (16383 / 32767)
-        const float inv = m > 0.0f ? (16383.0f / 32767.0f) / m : 0.0f;
-        const float sc = m * (1.0f / 16383.0f);
+        const float inv = m > 0.0f ? copysignf((16383.0f / 32767.0f) / m, f) : 0.0f;
+        const float sc = m * fabsf(f) * (1.0f / 16383.0f);
 #pragma unroll
         for (int k = 0; k < 12; ++k) w[k] = h16_pack(s[k].re * inv, s[k].im * inv);
         v4f v[3];

@@ -35,6 +35,14 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
 {
     typedef SpinorFmt<S> F;
     const R cb = (R)a.cb[T.lat];
+    if constexpr (std::is_same<S, H16>::value && !(EPI & (EPI_XPAY | EPI_DOTX_NORM | EPI_DOTY))) {
+        // 16-bit result cb * acc: cb enters the site scale, not the values
+        unsigned w[12];
+        const float sc =
+            F::template store_words<ST_STREAM>(spinor_buf<S>(a.out[T.lat], g.Vh, rhs), g.Vh, T.site, acc, w, cb);
+        if (EPI & EPI_NORM) q2 += h16_norm2(w, sc);
+        return;
+    }
     cx<R> out[12], xv[12];
     if (EPI & EPI_XPAY) {
         F::load(spinor_buf<S>(a.x[T.lat], g.Vh, rhs), g.Vh, T.site, xv);
@@ -281,7 +289,10 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             src.lane = lane;
             src.win = win;
             src.lk = (const unsigned *)lk;
-            hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
+            if constexpr (NOWIN)
+                hop_site_pk<DAG, 2>(g, c, src, acc);  // neighbour loads two directions ahead
+            else
+                hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
         } else {
             LdsSrc<S, LK, SLINK> src;
             src.in = ibuf;
