@@ -425,11 +425,63 @@ class Lattice:
     def set_tile(self, prec=PREC_F32, gauge_reals=12, rt=0, group=0, lds=-1):
         self._check(lib().fl_set_tile(self._h, prec, gauge_reals, rt, group, lds))
 
-    def autotune(self, prec=PREC_F32, gauge_reals=12, nrhs=1):
+    def autotune(self, prec=PREC_F32, gauge_reals=12, nrhs=1, cache=None):
+        """Time the hopping kernel over workgroup shapes and LDS modes and keep
+        the fastest for this lattice (fl_autotune).  cache: path of a JSON file
+        of earlier results keyed by device name, lattice extents, precision,
+        link reals and right-hand sides; a hit applies the stored shape
+        (fl_set_tile) without timing, a miss times and adds its result."""
+        key = None
+        if cache is not None:
+            key = tune_key(_device_name(self.device), self.dims, prec, gauge_reals, nrhs)
+            hit = tune_cache_load(cache).get(key)
+            if hit is not None:
+                self.set_tile(prec, gauge_reals, hit["rt"], hit["group"], hit["lds"])
+                return dict(hit, cached=True)
         rt, g, ld, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         self._check(lib().fl_autotune(self._h, prec, gauge_reals, nrhs, ctypes.byref(rt), ctypes.byref(g),
                                       ctypes.byref(ld), ctypes.byref(ms)))
-        return dict(rt=rt.value, group=g.value, lds=ld.value, ms=ms.value)
+        res = dict(rt=rt.value, group=g.value, lds=ld.value, ms=ms.value)
+        if cache is not None:
+            tune_cache_store(cache, key, res)
+        return dict(res, cached=False)
+
+
+def _device_name(device):
+    """Marketing name and architecture of a HIP device (torch's view of it)."""
+    import torch
+    p = torch.cuda.get_device_properties(device)
+    return f"{p.name} {getattr(p, 'gcnArchName', '')}".strip()
+
+
+def tune_key(device_name, dims, prec, gauge_reals, nrhs):
+    """Key of one autotuner result."""
+    return f"{device_name}|{'x'.join(str(int(d)) for d in dims)}|prec{int(prec)}|r{int(gauge_reals)}|nrhs{int(nrhs)}"
+
+
+def tune_cache_load(path):
+    """Autotuner results stored at path ({} if the file does not exist)."""
+    import json
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except FileNotFoundError:
+        return {}
+    if not isinstance(d, dict):
+        raise ValueError(f"{path}: not an autotuner cache")
+    return d
+
+
+def tune_cache_store(path, key, result):
+    """Add one result to the cache file (written to a temporary file and
+    renamed, so a reader never sees a partial file)."""
+    import json
+    d = tune_cache_load(path)
+    d[key] = {k: result[k] for k in ("rt", "group", "lds", "ms")}
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 def loops_stochastic_multi(lattices, noises, gammas, lp: SolverParams = None, hp: SolverParams = None,

@@ -58,6 +58,12 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
 #pragma unroll
         for (int k = 0; k < 12; ++k) out[k] = cb * acc[k];
     }
+    if constexpr ((EPI & EPI_SUBY16) != 0 && std::is_same<S, double>::value) {
+        cx<float> y16[12];
+        SpinorFmt<H16>::load(spinor_buf<H16>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, y16);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) out[k] = out[k] - cx<double>{(double)y16[k].re, (double)y16[k].im};
+    }
     if constexpr (std::is_same<S, H16>::value && !(EPI & (EPI_DOTX_NORM | EPI_DOTY))) {
         // 16-bit result without dot products: stored as words, its norm
         // summed from the stored integers (no decode back to FP32)
@@ -124,6 +130,51 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
         epilogue<S, EPI>(a, T, g, rhs, acc, q0, q1, q2);
     }
     reduce_partials<EPI>(a, T, q0, q1, q2);
+}
+
+// a 16-bit field read into FP64 arithmetic: the decoded values (the stored
+// integers times the site scale, rounded to FP32 exactly as every other
+// reader of the field decodes them) widen to FP64 without rounding
+struct H16WideSrc {
+    static constexpr bool PACKED_I16 = false;
+    static constexpr double LINK_UNIT = LinkF64R18::UNIT;
+    Buf in, gauge;
+    int Vh;
+    template <int MU>
+    __device__ __forceinline__ double spinor(int i, cx<double> s[12]) const
+    {
+        cx<float> f[12];
+        SpinorFmt<H16>::load(in, Vh, i, f);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) s[k] = cx<double>{(double)f[k].re, (double)f[k].im};
+        return 1.0;
+    }
+    __device__ __forceinline__ void link(int mu, int par, int i, cx<double> U[3][3]) const
+    {
+        link_load<LinkF64R18>(gauge, Vh, (mu * 2 + par) * LinkF64R18::NC * Vh * LinkF64R18::ESZ, i, U);
+    }
+};
+
+template <bool DAG>
+__global__ __launch_bounds__(512) void k_dslash_h16_wide(DslashArgs a)
+{
+    typedef LinkF64R18 LK;
+    TileInfo T = tile_info(a.B);
+    if (!T.valid_rhs) return;
+    if (a.mask && !a.mask[T.sys]) return;  // wave-uniform
+    const LatGeom &g = a.B.lat[T.lat];
+    const int rhs = __builtin_amdgcn_readfirstlane(T.rhs);
+    double q0 = 0, q1 = 0, q2 = 0;
+    if (T.valid_site) {
+        Coord c = cb_coords(g, a.par, T.site);
+        H16WideSrc src;
+        src.in = spinor_buf<H16>(a.in[T.lat], g.Vh, rhs);
+        src.gauge = make_buf(a.gauge[T.lat], (unsigned)(8u * LK::NC * LK::ESZ * (unsigned)g.Vh));
+        src.Vh = g.Vh;
+        cx<double> acc[12];
+        hop_site<DAG, double>(g, a.par, T.site, c, src, acc);
+        epilogue<double, EPI_PLAIN>(a, T, g, rhs, acc, q0, q1, q2);
+    }
 }
 
 template <typename S, class LK, bool SLINK>
@@ -356,6 +407,10 @@ void dispatch_epi(const DslashArgs &a, int epi, dim3 grid, dim3 block, hipStream
     case EPI_XPAY | EPI_DOTY: launch_one<S, LK, DAG, EPI_XPAY | EPI_DOTY>(a, grid, block, s); break;
     case EPI_XPAY | EPI_DOTX_NORM: launch_one<S, LK, DAG, EPI_XPAY | EPI_DOTX_NORM>(a, grid, block, s); break;
     case EPI_NORM: launch_one<S, LK, DAG, EPI_NORM>(a, grid, block, s); break;
+    case EPI_XPAY | EPI_NORM | EPI_SUBY16:
+        if constexpr (std::is_same<S, double>::value)
+            launch_one<S, LK, DAG, EPI_XPAY | EPI_NORM | EPI_SUBY16>(a, grid, block, s);
+        break;
     default: break;
     }
 }
@@ -386,7 +441,18 @@ size_t dslash_lds_bytes(LinkFormat fmt, int RT, int wsmax, int lds)
 bool dslash_epi_supported(int epi)
 {
     return epi == EPI_PLAIN || epi == EPI_XPAY || epi == (EPI_XPAY | EPI_NORM) ||
-           epi == (EPI_XPAY | EPI_DOTY) || epi == (EPI_XPAY | EPI_DOTX_NORM) || epi == EPI_NORM;
+           epi == (EPI_XPAY | EPI_DOTY) || epi == (EPI_XPAY | EPI_DOTX_NORM) || epi == EPI_NORM ||
+           epi == (EPI_XPAY | EPI_NORM | EPI_SUBY16);
+}
+
+void launch_dslash_h16_wide(const DslashArgs &a, bool dag, hipStream_t s)
+{
+    if (a.B.ntiles == 0) return;
+    dim3 grid(a.B.ntiles), block(FL_WAVE * a.B.RT);
+    if (dag)
+        hipLaunchKernelGGL((k_dslash_h16_wide<true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_dslash_h16_wide<false>), grid, block, 0, s, a);
 }
 
 void launch_dslash(LinkFormat fmt, const DslashArgs &a, bool dag, int epi, hipStream_t s)

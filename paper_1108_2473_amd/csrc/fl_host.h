@@ -37,7 +37,8 @@ enum {
     EPI_XPAY = 1,       // out = ca * x + cb * H in
     EPI_DOTY = 2,       // partial slots slot0, slot0+1: <y, out>
     EPI_DOTX_NORM = 4,  // slots slot0, slot0+1: <out, x>; slot0+2: |out|^2
-    EPI_NORM = 8        // slot0+2: |out|^2
+    EPI_NORM = 8,       // slot0+2: |out|^2
+    EPI_SUBY16 = 16     // FP64 fields only: out -= y, y a 16-bit field (its decoded values)
 };
 
 struct DslashArgs {
@@ -62,6 +63,9 @@ bool dslash_epi_supported(int epi);
 // LDS bytes the staged kernel needs for RT right-hand sides
 size_t dslash_lds_bytes(LinkFormat fmt, int RT, int wsmax, int lds);
 void launch_dslash(LinkFormat fmt, const DslashArgs &a, bool dag, int epi, hipStream_t s);
+// out = H in in FP64 arithmetic with FP64 links on a 16-bit input field (its
+// decoded values, widened exactly), FP64 output; RT <= 8
+void launch_dslash_h16_wide(const DslashArgs &a, bool dag, hipStream_t s);
 
 // per-system Krylov state kept on the device
 struct SysState {

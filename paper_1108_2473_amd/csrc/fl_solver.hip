@@ -158,14 +158,42 @@ struct Solver {
 
     // FP64 residual of the masked systems: rh = bh - Dhat xh (|rh|^2 -> slot 2),
     // then the iteration residual r = lo(rh) with <r0, r>, |r|^2 (slots 3..5);
-    // init = 1 also restarts the recurrence (r0 = p = r, xl = 0)
+    // init = 1 also restarts the recurrence (r0 = p = r, xl = 0).
+    // With 16-bit iteration vectors rh = bh - Dhat xh holds between
+    // replacements, and the update is rh -= Dhat xl (FP64 arithmetic on the
+    // decoded values of xl, the same values that xh += xl adds), which reads
+    // xl instead of xh in the first hop and needs no rh = bh - xh pass; the
+    // rounding this accumulates stays at the FP64 level of |b| (the stopping
+    // rule on the full operator is checked separately by the callers)
     void replace_residual(const int *msk, int init)
     {
-        blas(vf, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                  // xh += xl, xl = 0
-        blas(VEC_F64, OP_SUB_HI, {&RH, &BH, &XH}, 0, 0, msk);        // rh = bh - xh
-        dslash(LINK_F64_R18, false, 1, XH, T64, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, false, false);
-        dslash(LINK_F64_R18, false, 0, T64, RH, &RH, nullptr, 1.0, pos_k2, EPI_XPAY | EPI_NORM, 0, msk, false,
-               false);
+        if (vf == VEC_H16) {
+            DslashArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.B = B64;
+            a.par = 1;
+            a.nsys = nsys;
+            a.mask = msk;
+            a.partial = partial;
+            for (int l = 0; l < B.nlat; ++l) {
+                a.in[l] = XL.p[l];
+                a.out[l] = T64.p[l];
+                a.gauge[l] = gauge_hi[l];
+                a.ca[l] = 1.0;
+                a.cb[l] = 1.0;
+            }
+            launch_dslash_h16_wide(a, false, st);                      // t = H_oe xl
+            dslash(LINK_F64_R18, false, 0, T64, RH, &RH, &XL, 1.0, pos_k2, EPI_XPAY | EPI_NORM | EPI_SUBY16, 0, msk,
+                   false, false);                                      // rh += k^2 H_eo t - xl
+            blas(vf, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                // xh += xl, xl = 0
+        } else {
+            blas(vf, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                // xh += xl, xl = 0
+            blas(VEC_F64, OP_SUB_HI, {&RH, &BH, &XH}, 0, 0, msk);      // rh = bh - xh
+            dslash(LINK_F64_R18, false, 1, XH, T64, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, false,
+                   false);
+            dslash(LINK_F64_R18, false, 0, T64, RH, &RH, nullptr, 1.0, pos_k2, EPI_XPAY | EPI_NORM, 0, msk, false,
+                   false);
+        }
         blas(vf, OP_HI_TO_LO, {&R, &RH, &R0, &P, &XL}, init, 3, msk);
     }
 

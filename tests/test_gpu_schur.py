@@ -123,3 +123,19 @@ def test_solver_with_16_waves_per_workgroup(F, lds):
     assert all(i["converged"] and i["true_resid"] <= 1e-10 for i in info), info
     r = O.apply_D(U, x[3], dims, -1, KAPPA) - b[3]
     assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b[3]) * 1.01
+
+
+def test_autotune_cache_hit(F, tmp_path):
+    """A first autotune call times and stores its result; a second call with
+    the same key applies the stored shape without timing."""
+    lat, U = lattice(F, (4, 4, 4, 8))
+    path = str(tmp_path / "tune.json")
+    try:
+        first = lat.autotune(prec=3, gauge_reals=12, nrhs=8, cache=path)
+        second = lat.autotune(prec=3, gauge_reals=12, nrhs=8, cache=path)
+    finally:
+        lat.set_tile(prec=3, gauge_reals=12, rt=0, group=0, lds=-1)
+    assert not first["cached"] and second["cached"]
+    assert (first["rt"], first["group"], first["lds"]) == (second["rt"], second["group"], second["lds"])
+    assert first["lds"] in range(0, 5) and first["ms"] > 0
+    assert len(F.tune_cache_load(path)) == 1
