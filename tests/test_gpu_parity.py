@@ -286,6 +286,29 @@ def test_gradient_vs_oracle(F, bc):
     assert abs(dk - dko) <= 1e-9 * abs(dko)
 
 
+@pytest.mark.parametrize("solver", [0, 1])
+def test_16bit_reliable_updates_keep_the_residual(F, solver):
+    """With 16-bit iteration vectors the FP64 residual is carried from one
+    replacement to the next as rh -= Dhat xl (not recomputed from x): over
+    several replacements (7-8 per solve here, one per host check at most) its
+    rounding must stay at the FP64 level: a carried residual that drifted
+    below the true one would stop the iteration early, and the solution would
+    miss the stopping rule on the full operator, recomputed here by the
+    oracle (the reported residual must agree with the oracle's too)."""
+    dims = (8, 4, 4, 8)
+    lat, U = make(F, dims, 0.5, 0.14, -1, 31)
+    b = S.random_spinors(dims, 6, 32)
+    tol = 1e-12
+    x, info = lat.solve(b, F.SolverParams(tol=tol, inner_prec=F.PREC_H16, gauge_reals=12, solver=solver))
+    assert all(i["converged"] for i in info), info
+    assert min(i["updates"] for i in info) >= 5, info
+    r = b - O.apply_D(U, x, dims, -1, 0.14)
+    rel = np.linalg.norm(r.reshape(6, -1), axis=1) / np.linalg.norm(b.reshape(6, -1), axis=1)
+    assert np.all(rel <= 1.05 * tol), rel
+    for k in range(6):
+        assert abs(info[k]["true_resid"] - rel[k]) <= 0.05 * rel[k] + 1e-15
+
+
 def test_cgnr_16bit_fast_convergence(F):
     """16-bit CGNR on a small, well-conditioned lattice (4^4, kappa = 0.1),
     where an iteration cuts the residual ~3x: point sources (sparse) and a
