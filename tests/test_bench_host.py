@@ -1,0 +1,45 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU contract and the rule
+that counter traffic is reported only for the kernel sources it was taken on."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout
+
+
+def test_source_hash_is_stable_and_hex():
+    h = bench.kernel_source_hash()
+    assert h == bench.kernel_source_hash() and len(h) == 64 and int(h, 16) >= 0
+
+
+def _fake_profile(tmp_path, sha, traffic):
+    p = tmp_path / "hopping_h16r12_stoch_16x16x16x32.md"
+    p.write_text(f"# summary\n\n    kernel_source_sha256: {sha}\n    traffic_bytes_per_launch: {traffic}\n")
+    return str(p)
+
+
+def test_traffic_only_for_matching_sources(tmp_path, monkeypatch):
+    good = _fake_profile(tmp_path, bench.kernel_source_hash(), 3478292881)
+    monkeypatch.setattr(bench, "traffic_profile", lambda prec: good)
+    assert bench.profiled_traffic("h16") == 3478292881.0
+    stale = _fake_profile(tmp_path, "0" * 64, 3478292881)
+    monkeypatch.setattr(bench, "traffic_profile", lambda prec: stale)
+    assert bench.profiled_traffic("h16") is None
+    monkeypatch.setattr(bench, "traffic_profile", lambda prec: str(tmp_path / "missing.md"))
+    assert bench.profiled_traffic("h16") is None
+
+
+def test_committed_profiles_carry_machine_readable_fields():
+    for prec in ("h16", "f32"):
+        txt = open(bench.traffic_profile(prec)).read()
+        assert "kernel_source_sha256:" in txt and "traffic_bytes_per_launch:" in txt
+        assert "rocprofv3 --kernel-trace --stats" in txt
