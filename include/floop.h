@@ -90,10 +90,13 @@ enum { FL_DIL_TIME = 1, FL_DIL_SPIN = 2, FL_DIL_COLOUR = 4, FL_DIL_EVENODD = 8,
  *              the links as 16-bit fixed point (12 reals, 24 bytes), with
  *              FP32 arithmetic (the paper ran mixed-precision GPU solvers,
  *              Sec. II; this is the narrowest storage offered here).
- *              For F32/BF16/H16 the FP64 residual b - Dx is recomputed and
- *              the iteration residual replaced whenever the latter has
- *              dropped by `delta` since the last replacement (reliable
- *              updates).
+ *              For F32/BF16/H16 the iteration residual is replaced by the
+ *              FP64 residual whenever it has dropped by `delta` since the
+ *              last replacement (reliable updates): F32 and BF16 recompute
+ *              b - Dx from the FP64 solution; H16 carries the FP64
+ *              residual, subtracting D applied in FP64 to the 16-bit
+ *              correction that it then adds to the FP64 solution.  Every
+ *              solve's result is checked on the full operator in FP64.
  *  gauge_reals 18 (full links) or 12 (rows 0 and 1; row 2 rebuilt as
  *              conj(row0 x row1)) for the F32 inner operator; BF16 and H16
  *              need 12.
