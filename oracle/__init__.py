@@ -34,6 +34,7 @@ def _load():
     i, d, l, u64 = ctypes.c_int, ctypes.c_double, ctypes.c_long, ctypes.c_uint64
     ip, dp, lp = _c_int_p, _c_double_p, _c_long_p
     lib.or_num_threads.restype = i
+    lib.or_set_num_threads.argtypes = [i]
     lib.or_gamma.argtypes = [i, i, dp]
     lib.or_hop.argtypes = [ip, i, i, dp, dp, dp, i, i]
     lib.or_apply_D.argtypes = [ip, i, i, d, dp, dp, dp, i, i]
@@ -76,6 +77,11 @@ def _ints(seq):
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel regions in this thread (n >= 1)."""
+    _load().or_set_num_threads(int(n))
 
 
 def gamma(mask: int, basis: int = 0) -> np.ndarray:
@@ -355,16 +361,21 @@ def pion_correlator(U, dims, bc_t, kappa, y0, mom, alpha=0.0, n=0, norm=1.0, sme
 
 
 # ---------------------------------------------------------------------------
-# the paper's comparison of stochastic methods with the exact loops (Sec. IV),
-# composed from the oracle's own loops, projection and correlator
+# the paper's comparison of stochastic methods with the exact loops (Sec. III,
+# figures "compare dilution" and "truncated"), composed from the oracle's own
+# loops, projection and correlator
 # ---------------------------------------------------------------------------
-def dilution_study(configs, dims, bc_t, kappa, n_noise, schemes, tsm, seed, tol_hp, tol_lp, tol_exact=1e-13):
+def dilution_study(configs, dims, bc_t, kappa, n_noise, schemes, tsm, seed, tol_hp, tol_lp, tol_exact=1e-13,
+                   tsm_dilution=0, with_exact=True):
     """D(t) at p = 0 for Gamma = g5 per configuration: exact (point sources on
     every site), plain stochastic with complex Z2 noise for each dilution mask
     in `schemes` (name -> mask) and N noise vectors (unbiased mean over pairs
     r != s of per-vector loops), and the truncated solver method for each
     (n_lp, n_hp) in `tsm` (two independent halves correlated with each other;
-    half h starts at noise index h (n_lp + n_hp) / 2 of seed + 1).
+    half h starts at noise index h (n_lp + n_hp) / 2 of seed + 1), its noise
+    diluted with the mask `tsm_dilution` (Sec. II: the TSM combines with
+    dilution; 0 = undiluted).  with_exact=False skips the exact evaluation
+    (out["exact"] is then None).
     Configuration c uses seed + 1000 c.  Returns dicts of [nconf][T] arrays."""
     T = dims[3]
     Vs = dims[0] * dims[1] * dims[2]
@@ -372,9 +383,10 @@ def dilution_study(configs, dims, bc_t, kappa, n_noise, schemes, tsm, seed, tol_
     out = {"exact": [], "stochastic": {}, "tsm": {}}
     for ci, U in enumerate(configs):
         cseed = seed + 1000 * ci
-        Lx = loops_exact(U, dims, bc_t, kappa, list(range(T)), [15], tol=tol_exact)
-        P = momentum_project(Lx, dims, zero)
-        out["exact"].append(disconnected_correlator(P, P, Vs, [(0, 0)])[0, 0])
+        if with_exact:
+            Lx = loops_exact(U, dims, bc_t, kappa, list(range(T)), [15], tol=tol_exact)
+            P = momentum_project(Lx, dims, zero)
+            out["exact"].append(disconnected_correlator(P, P, Vs, [(0, 0)])[0, 0])
         for name, mask in schemes.items():
             per = [momentum_project(loops_stochastic(U, dims, bc_t, kappa, NOISE_CZ2, cseed, r, 1, mask, 0, T,
                                                      [15], tol=tol_hp), dims, zero)[0]
@@ -388,11 +400,12 @@ def dilution_study(configs, dims, bc_t, kappa, n_noise, schemes, tsm, seed, tol_
                 out["stochastic"].setdefault((name, N), []).append(acc / (N * (N - 1)))
         for (n_lp, n_hp) in tsm:
             halves = [momentum_project(loops_tsm(U, dims, bc_t, kappa, NOISE_CZ2, cseed + 1, h * (n_lp + n_hp) // 2,
-                                                 n_lp // 2, n_hp // 2, tol_lp, tol_hp, 0, 0, T, [15]), dims, zero)
+                                                 n_lp // 2, n_hp // 2, tol_lp, tol_hp, tsm_dilution, 0, T, [15]), dims,
+                                                 zero)
                       for h in range(2)]
             out["tsm"].setdefault((n_lp, n_hp), []).append(
                 disconnected_correlator(halves[0], halves[1], Vs, [(0, 0)])[0, 0])
-    out["exact"] = np.array(out["exact"])
+    out["exact"] = np.array(out["exact"]) if with_exact else None
     out["stochastic"] = {k: np.array(v) for k, v in out["stochastic"].items()}
     out["tsm"] = {k: np.array(v) for k, v in out["tsm"].items()}
     return out

@@ -527,6 +527,16 @@ int or_num_threads(void)
 #endif
 }
 
+/* threads of the later parallel regions of the calling thread (n >= 1) */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* hopping term with parity restriction (out_parity -1: all sites) */
 void or_hop(const int *dims, int bc_t, int basis, const double *U, const double *in,
             double *out, int out_parity, int dagger)

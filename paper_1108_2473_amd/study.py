@@ -1,7 +1,8 @@
-"""The paper's comparison of stochastic methods with the exact loops (Sec. IV):
-the disconnected pseudoscalar two-point function D(t) at p = 0 (Eq.
-all_dis_corr, Gamma = g5) on an ensemble of gauge configurations, computed
-exactly (all-to-all: point sources on every site of every timeslice) and
+"""The paper's comparison of stochastic methods with the exact loops (Sec.
+III, figures "compare dilution" and "truncated"): the disconnected
+pseudoscalar two-point function D(t) at p = 0 (Eq. all_dis_corr,
+Gamma = g5) on an ensemble of gauge configurations, computed exactly
+(all-to-all: point sources on every site of every timeslice) and
 stochastically as a function of the number of inversions, for colour, spin,
 even-odd and cubic dilution and for the truncated solver method.
 

@@ -1,8 +1,8 @@
-"""The comparison of stochastic methods with the exact loops (Sec. IV) run by
-the GPU library and by the oracle on the same tiny ensemble with the same
-noise: every per-configuration D(t) agrees; and on a larger ensemble the
-stochastic estimates approach the exact value as the number of inversions
-grows."""
+"""The comparison of stochastic methods with the exact loops (Sec. III,
+figures "compare dilution" and "truncated") run by the GPU library and by
+the oracle on the same tiny ensemble with the same noise: every
+per-configuration D(t) agrees; and on a larger ensemble the stochastic
+estimates approach the exact value as the number of inversions grows."""
 import numpy as np
 import pytest
 

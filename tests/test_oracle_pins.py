@@ -270,7 +270,8 @@ def test_solver_methods_agree_with_dense():
 
 
 def test_schur_operator_vs_dense_blocks():
-    """Dhat = 1 - D_eo D_oe (D_oo = 1) on even sites, built from dense D blocks."""
+    """Dhat = 1 - D_eo D_oe (D_oo = 1) on even sites, built from dense D blocks,
+    and Dhat^+ as the conjugate transpose of that block."""
     dims = (4, 2, 2, 4)
     V = S.volume(dims)
     U = S.random_links(dims, 0.5, 41)
@@ -285,6 +286,10 @@ def test_schur_operator_vs_dense_blocks():
     got = O.apply_Dhat(U, x, dims, bc, kappa).reshape(-1)
     assert np.abs(got[od]).max() == 0.0
     assert np.abs(got[ev] - Dhat @ x.reshape(-1)[ev]).max() < 1e-13
+    # dagger = 1 is the conjugate transpose of the same dense block
+    got = O.apply_Dhat(U, x, dims, bc, kappa, dagger=True).reshape(-1)
+    assert np.abs(got[od]).max() == 0.0
+    assert np.abs(got[ev] - Dhat.conj().T @ x.reshape(-1)[ev]).max() < 1e-13
 
 
 def test_neumann_series():
