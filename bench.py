@@ -46,15 +46,8 @@ def traffic_profile(prec):
 
 def kernel_source_hash():
     """SHA-256 over the HIP sources and the C header, in sorted path order."""
-    import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1108_2473_amd", "csrc")
-    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h")))
-    for f in files + [os.path.join(ROOT, "include", "floop.h")]:
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    from paper_1108_2473_amd import build
+    return build.source_hash()
 
 
 def profiled_traffic(prec):
@@ -75,13 +68,69 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def diluted_source(xi, t, spin, col, dims):
-    """eta = P_d xi for the time/spin/colour component (t, spin, col)."""
+def cpu_model():
+    """Model name of the host CPU (/proc/cpuinfo), or the platform string."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(U, b, x_mp, dims, bc, kappa, gam):
+    """The FP64 oracle (even-odd BiCGStab, OpenMP over sites) on a bounded
+    sample of the workload: two of its diluted sources solved to 1e-12 with
+    every thread of the process, then the same solver single-threaded for 40
+    iterations of one source, its per-iteration time scaled to the threaded
+    run's iteration count.  Returns (cpu_baseline dict, loop error of the
+    mixed-precision GPU solution of b[0] against the oracle's)."""
     import numpy as np
+    import oracle as O
+    ncpu = 2
+    nthr = O.num_threads()
+    t2 = time.perf_counter()
+    x_or, it_or, res_or, fails = O.solve(U, b[:ncpu], dims, bc, kappa, tol=1e-12, max_iter=1200)
+    t_or = time.perf_counter() - t2
+    if fails:
+        raise SystemExit(f"oracle baseline: {fails} solves missed 1e-12")
+    n1 = 40
+    O.set_num_threads(1)
+    try:
+        t3 = time.perf_counter()
+        O.solve(U, b[:1], dims, bc, kappa, tol=1e-12, max_iter=n1)
+        t_1 = time.perf_counter() - t3
+    finally:
+        O.set_num_threads(nthr)
+    it_mean = float(np.mean(it_or[:ncpu]))
+    rate_1 = 1.0 / (t_1 / n1 * it_mean)
+    cpu = {"value": ncpu / t_or, "unit": "solves/s", "cores": nthr, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "single_thread_value": rate_1,
+           "sample": f"{ncpu} spin-colour-time diluted Z4 sources of the same 16^3x32 workload (timeslices 0 "
+                     f"and 5) solved by the FP64 oracle (even-odd BiCGStab, "
+                     f"{'/'.join(str(int(v)) for v in it_or[:ncpu])} iterations, |Dx-b|/|b| <= "
+                     f"{max(res_or[:ncpu]):.1e}) in {t_or:.1f} s on {nthr} threads; single-threaded: "
+                     f"{n1} iterations of one source in {t_1:.1f} s, scaled to {it_mean:.0f} iterations "
+                     f"per solve"}
+    # loop error vs FP64: this source's contribution eta^+ Gamma phi on its timeslice
     Vs = dims[0] * dims[1] * dims[2]
-    eta = np.zeros_like(xi)
-    eta[Vs * t:Vs * (t + 1), spin, col] = xi[Vs * t:Vs * (t + 1), spin, col]
-    return eta
+    e = b[0, :Vs]
+    errs = []
+    l1 = None
+    for g in gam:
+        G = O.gamma(g)
+        lg = np.einsum("sac,ab,sbc->s", e.conj(), G, x_mp[0, :Vs])
+        lo = np.einsum("sac,ab,sbc->s", e.conj(), G, x_or[0, :Vs])
+        if l1 is None:
+            l1 = np.abs(lo).max()
+        errs.append(np.abs(lg - lo).max() / l1)
+    loop_err = max(errs)
+    log(f"[bench] oracle {t_or:.1f}s for {ncpu} solves ({nthr} threads), single thread {rate_1:.4f} solves/s "
+        f"(extrapolated); loop rel err vs FP64 {loop_err:.2e}")
+    return cpu, loop_err
 
 
 def main():
@@ -151,12 +200,27 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     loops = []
+    solve_stats = []
     for k in range(args.steps):
         loops.append(step(k))
+        solve_stats.append(lat.last_stats())  # host copy of the call's statistics (no device work)
         log(f"[bench] step {k} done at {time.perf_counter() - t0:.2f}s "
             f"({lat.profile_read(fl.PROF_DSLASH)['launches']} hopping launches so far)")
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
+    # every timed solve must have met the stopping rule on the full operator
+    conv = np.concatenate([st["converged"] for st in solve_stats])
+    resid = np.concatenate([st["true_resid"] for st in solve_stats])
+    iters = np.concatenate([st["iters"] for st in solve_stats])
+    upd = np.concatenate([st["updates"] for st in solve_stats])
+    if len(conv) != solves_per_step * args.steps or not conv.all() or not (resid <= 1e-12).all():
+        raise SystemExit(f"bench: {int((~conv).sum())} of {len(conv)} timed solves missed 1e-12 "
+                         f"(largest residual {resid.max():.3e})")
+    solves_summary = {"solves": int(len(conv)), "converged": int(conv.sum()),
+                      "max_true_resid_full_operator": float(resid.max()),
+                      "iterations_mean": round(float(iters.mean()), 1), "iterations_max": int(iters.max()),
+                      "fp64_updates_mean": round(float(upd.mean()), 2)}
+    log(f"[bench] timed solves: {solves_summary}")
     prof = lat.profile_read(fl.PROF_DSLASH)
     lat.profile_enable(fl.PROF_DSLASH, False)
     value = solves_per_step * args.steps / T
@@ -274,16 +338,19 @@ def main():
         lg.close()
 
     # accuracy and the plain FP64 single-RHS reference on sources of the same workload
-    import oracle as O
-    xi = O.noise(O.NOISE_Z4, W["noise_seed"], 0, dims)
-    srcs = [diluted_source(xi, t, s, 0, dims) for (t, s) in [(0, 0), (5, 1), (17, 2), (31, 3)]]
-    b = np.stack(srcs[:max(1, args.fp64_rhs)])
+    # the plain FP64 single-RHS GPU solve (the denominator of the batched
+    # mixed-precision speed-up) on sources of the workload's shape: Z4 values
+    # on one timeslice, spin and colour each (seeded numpy, the same arrays for
+    # the GPU and for the oracle below)
+    comps = [(0, 0, 0), (5, 1, 0), (17, 2, 0), (31, 3, 0)]
+    nfp64 = max(1, args.fp64_rhs)
+    b = S.z4_diluted_sources(dims, comps[:max(2, nfp64)], W["noise_seed"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for k in range(b.shape[0]):
+    for k in range(nfp64):
         x64, info64 = lat.solve(b[k:k + 1], fl.SolverParams(tol=1e-12, inner_prec=fl.PREC_F64, gauge_reals=18))
     torch.cuda.synchronize()
-    fp64_rate = b.shape[0] / (time.perf_counter() - t1)
+    fp64_rate = nfp64 / (time.perf_counter() - t1)
     x_mp, info_mp = lat.solve(b[:1], fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, solver=solver))
     log(f"[bench] FP64 single-RHS GPU: {fp64_rate:.2f} solves/s ({info64[0]['iters']} iterations); "
         f"mixed: {info_mp[0]['iters']} iterations, {info_mp[0]['updates']} FP64 updates")
@@ -291,31 +358,7 @@ def main():
     cpu = None
     loop_err = None
     if not args.no_cpu_baseline:
-        # a bounded sample of the timed workload: two of its diluted sources
-        ncpu = 2
-        t2 = time.perf_counter()
-        x_or, it_or, res_or, fails = O.solve(U, np.stack(srcs[:ncpu]), dims, bc, kappa, tol=1e-12, max_iter=1200)
-        t_or = time.perf_counter() - t2
-        cpu = {"value": ncpu / t_or, "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
-               "sample": f"{ncpu} spin-colour-time diluted Z4 sources of the same 16^3x32 workload (timeslices "
-                         f"0 and 5) solved by the FP64 oracle (even-odd BiCGStab, "
-                         f"{'/'.join(str(int(v)) for v in it_or[:ncpu])} iterations, |Dx-b|/|b| <= "
-                         f"{max(res_or[:ncpu]):.1e}) in {t_or:.1f} s"}
-        # loop error vs FP64: this source's contribution eta^+ Gamma phi on its timeslice
-        Vs = dims[0] * dims[1] * dims[2]
-        e = b[0, :Vs]
-        errs = []
-        l1 = None
-        for g in gam:
-            G = O.gamma(g)
-            lg = np.einsum("sac,ab,sbc->s", e.conj(), G, x_mp[0, :Vs])
-            lo = np.einsum("sac,ab,sbc->s", e.conj(), G, x_or[0, :Vs])
-            if l1 is None:
-                l1 = np.abs(lo).max()
-            errs.append(np.abs(lg - lo).max() / l1)
-        loop_err = max(errs)
-        log(f"[bench] oracle {t_or:.1f}s for {ncpu} solves ({O.num_threads()} threads); "
-            f"loop rel err vs FP64 {loop_err:.2e}")
+        cpu, loop_err = cpu_baseline(U, b, x_mp, dims, bc, kappa, gam)
 
     bytes_per_launch = prof["bytes"] / max(1, prof["launches"])
     traffic = profiled_traffic(args.prec)
@@ -369,6 +412,7 @@ def main():
             "algorithmic_bytes_per_launch": round(bytes_per_launch),
         },
         "cpu_baseline": cpu,
+        "timed_solves": solves_summary,
         "fp64_single_rhs_gpu_solves_per_s": round(fp64_rate, 3),
         "speedup_vs_fp64_single_rhs": round(value / fp64_rate, 3),
         "loop_rel_err_vs_fp64": loop_err,

@@ -110,6 +110,17 @@ enum { FL_DIL_TIME = 1, FL_DIL_SPIN = 2, FL_DIL_COLOUR = 4, FL_DIL_EVENODD = 8,
  *              deterministic function of the source, independent of the
  *              batch it is solved in.
  *  batch       maximum right-hand sides per device batch (0: default).
+ *  max_outer   FP64 residual replacements (outer cycles of the mixed-
+ *              precision solve) per right-hand side; 0: no limit.  A
+ *              right-hand side that reaches it without meeting tol stops
+ *              with FL_ERR_NOCONV.
+ * Every solve that is not truncated is accepted on the FP64 residual of the
+ * FULL operator, |b - D x| / |b| with x = (x_e, x_o) and x_o = b_o +
+ * kappa H_oe x_e, recomputed after the Schur solve (fl_solve and every
+ * fl_loops_* call); a right-hand side above tol is reported as not
+ * converged.  In the terms of a classic outer/inner mixed-precision solver:
+ * delta is the inner (per-outer-cycle) reduction target, updates are the
+ * outer cycles, and truncated = 1 is an inner-only (LP) solve.
  */
 typedef struct {
     int solver;
@@ -120,15 +131,17 @@ typedef struct {
     double delta;
     int truncated;
     int batch;
+    int max_outer;
 } fl_solver_params;
 
 /* per right-hand side */
 typedef struct {
     int iters;          /* Krylov iterations */
-    int updates;        /* FP64 residual replacements */
-    int converged;      /* 1 if true_resid <= tol */
+    int updates;        /* FP64 residual replacements (outer cycles) */
+    int converged;      /* 1 if true_resid <= tol (truncated: its own residual reached tol) */
     double true_resid;  /* |D x - b| / |b| recomputed in FP64 on the full operator
                            (truncated solves: the iteration's own estimate) */
+    double seconds;     /* wall time of the device batch this right-hand side was solved in */
 } fl_solver_stats;
 
 /*
@@ -155,7 +168,7 @@ typedef struct {
 
 /* Fill p with defaults: BiCGStab, tol 1e-12, max_iter 20000, FP32 inner
  * with 12-real links, delta 0 (the solver's default for the inner
- * precision), not truncated, default batch. */
+ * precision), not truncated, default batch, no limit on outer cycles. */
 void fl_solver_params_default(fl_solver_params *p);
 
 /* Library version string. */
@@ -222,7 +235,11 @@ fl_status fl_loops_exact_sites(fl_ctx *ctx, const long long *sites, long long ns
 
 /* Stochastic / truncated-solver-method loops (fl_noise_params above).
  * lp: solver of the first ensemble; hp: solver of the correction ensemble
- * (ignored when n_hp = 0).  L: [ngamma][t_end-t_begin][Vs][2]. */
+ * (ignored when n_hp = 0).  L: [ngamma][t_end-t_begin][Vs][2].
+ * FL_ERR_NOCONV (or FL_ERR_BREAKDOWN) when any solve of either ensemble
+ * missed its tolerance (truncated solves: their own residual within
+ * max_iter); L then holds the estimate from the best iterates and
+ * fl_last_stats names the solves. */
 fl_status fl_loops_stochastic(fl_ctx *ctx, const fl_noise_params *np, const int *gammas,
                               int ngamma, const fl_solver_params *lp,
                               const fl_solver_params *hp, double *L, fl_where where);
@@ -338,6 +355,20 @@ fl_status fl_smear(fl_ctx *ctx, double *psi, int nrhs, double alpha, int n, doub
 fl_status fl_pion_corr(fl_ctx *ctx, long long y0, const fl_solver_params *p, double alpha, int n,
                        double norm, int smear_source, int smear_sink, const int *mom, int nmom,
                        double *C, fl_where where);
+
+/* Per-solve statistics of the last call on ctx that solved (fl_solve,
+ * fl_loops_exact, fl_loops_exact_sites, fl_loops_stochastic, its share of
+ * fl_loops_stochastic_multi, fl_loops_grad, fl_pion_corr), one entry per
+ * right-hand side in the order of that call: fl_solve its right-hand
+ * sides; the exact loops and the gradient 12 per site (12 k + 3 spin +
+ * colour for the k-th site solved); the stochastic loops one per dilution
+ * component, for each LP noise vector (time, spin, colour, space class,
+ * the slowest first), then for each HP noise vector its LP solves followed
+ * by its HP solves; fl_pion_corr the 12 spin-colour sources.  *n receives
+ * the count; at most cap entries are written to stats (host memory; NULL
+ * with cap 0 asks for the count only).  A call that failed before solving
+ * leaves the previous statistics in place. */
+fl_status fl_last_stats(const fl_ctx *ctx, fl_solver_stats *stats, long long cap, long long *n);
 
 /* Text of the last error of ctx (or of the last failed fl_create when ctx
  * is NULL). */

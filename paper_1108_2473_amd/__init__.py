@@ -34,20 +34,28 @@ _STATUS = {0: "FL_OK", -1: "FL_ERR_ARG", -2: "FL_ERR_STATE", -3: "FL_ERR_DEVICE"
 
 
 class FloopError(RuntimeError):
-    def __init__(self, status, msg):
+    """A non-zero fl_status.  For FL_ERR_NOCONV and FL_ERR_BREAKDOWN of a call
+    that returns arrays, `result` holds what the call returned (built from the
+    best iterates); fl_last_stats names the solves (Lattice.last_stats)."""
+
+    def __init__(self, status, msg, result=None):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
         self.status = status
+        self.result = result
+
+
+NOCONV, BREAKDOWN = -5, -6
 
 
 class _SolverParams(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("inner_prec", ctypes.c_int), ("gauge_reals", ctypes.c_int), ("delta", ctypes.c_double),
-                ("truncated", ctypes.c_int), ("batch", ctypes.c_int)]
+                ("truncated", ctypes.c_int), ("batch", ctypes.c_int), ("max_outer", ctypes.c_int)]
 
 
 class _SolverStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("updates", ctypes.c_int), ("converged", ctypes.c_int),
-                ("true_resid", ctypes.c_double)]
+                ("true_resid", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
 class _NoiseParams(ctypes.Structure):
@@ -67,10 +75,11 @@ class SolverParams:
     delta: float = 0.0  # 0: the library default (0.1; 0.3 for 16-bit storage)
     truncated: bool = False
     batch: int = 0
+    max_outer: int = 0  # FP64 residual replacements per right-hand side (0: no limit)
 
     def c(self):
         return _SolverParams(self.solver, self.tol, self.max_iter, self.inner_prec, self.gauge_reals,
-                             self.delta, int(self.truncated), self.batch)
+                             self.delta, int(self.truncated), self.batch, self.max_outer)
 
 
 @dataclass
@@ -143,10 +152,12 @@ def lib():
                                ctypes.POINTER(i), i, vp, i]
     L.fl_disconnected_corr.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(i), i, vp, i]
     L.fl_solver_params_default.argtypes = [ctypes.POINTER(_SolverParams)]
+    L.fl_last_stats.argtypes = [vp, ctypes.POINTER(_SolverStats), ll, ctypes.POINTER(ll)]
     for name in ("fl_create", "fl_destroy", "fl_set_stream", "fl_set_gauge", "fl_set_kappa", "fl_apply_D",
                  "fl_apply_schur", "fl_solve", "fl_loops_exact", "fl_loops_exact_sites", "fl_loops_stochastic",
                  "fl_loops_stochastic_multi", "fl_loops_grad", "fl_profile_enable", "fl_profile_read",
-                 "fl_bench_dslash", "fl_set_tile", "fl_autotune", "fl_momentum_project", "fl_disconnected_corr", "fl_smear", "fl_pion_corr"):
+                 "fl_bench_dslash", "fl_set_tile", "fl_autotune", "fl_momentum_project", "fl_disconnected_corr", "fl_smear",
+                 "fl_pion_corr", "fl_last_stats"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -227,9 +238,10 @@ class Lattice:
         except Exception:
             pass
 
-    def _check(self, st):
+    def _check(self, st, result=None):
         if st != 0:
-            raise FloopError(st, lib().fl_last_error(self._h).decode())
+            raise FloopError(st, lib().fl_last_error(self._h).decode(),
+                             result if st in (NOCONV, BREAKDOWN) else None)
 
     def _stream_for(self, arr: _Arr):
         if arr.torch:
@@ -291,8 +303,24 @@ class Lattice:
         if check and st not in (0,):
             self._check(st)
         info = [dict(iters=s.iters, updates=s.updates, converged=bool(s.converged),
-                     true_resid=s.true_resid) for s in stats[:nrhs]]
+                     true_resid=s.true_resid, seconds=s.seconds) for s in stats[:nrhs]]
         return out, info
+
+    def last_stats(self):
+        """Per-solve statistics of the last solving call on this lattice
+        (fl_last_stats): numpy arrays iters, updates, converged (bool),
+        true_resid and seconds, one entry per right-hand side in the order of
+        that call."""
+        n = ctypes.c_longlong()
+        self._check(lib().fl_last_stats(self._h, None, 0, ctypes.byref(n)))
+        buf = (_SolverStats * max(1, n.value))()
+        self._check(lib().fl_last_stats(self._h, buf, n.value, ctypes.byref(n)))
+        rows = buf[:n.value]
+        return dict(iters=np.array([r.iters for r in rows], dtype=np.int64),
+                    updates=np.array([r.updates for r in rows], dtype=np.int64),
+                    converged=np.array([bool(r.converged) for r in rows], dtype=bool),
+                    true_resid=np.array([r.true_resid for r in rows], dtype=np.float64),
+                    seconds=np.array([r.seconds for r in rows], dtype=np.float64))
 
     def _out(self, shape, device):
         if device:
@@ -313,7 +341,8 @@ class Lattice:
         if want_S:
             S, sp, _ = self._out((nt, self.Vs, 4, 4), device)
         self._check(lib().fl_loops_exact(self._h, t_arr, nt, g_arr, ng, ctypes.byref(params.c()),
-                                         ctypes.c_void_p(lp), ctypes.c_void_p(sp) if want_S else None, where))
+                                         ctypes.c_void_p(lp), ctypes.c_void_p(sp) if want_S else None, where),
+                    (L, S) if want_S else L)
         return (L, S) if want_S else L
 
     def loops_exact_sites(self, sites, gammas, params: SolverParams = None, want_S=False, device=False):
@@ -327,7 +356,8 @@ class Lattice:
             S, sp, _ = self._out((sites.size, 4, 4), device)
         self._check(lib().fl_loops_exact_sites(
             self._h, sites.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), sites.size, g_arr, ng,
-            ctypes.byref(params.c()), ctypes.c_void_p(lp), ctypes.c_void_p(sp) if want_S else None, where))
+            ctypes.byref(params.c()), ctypes.c_void_p(lp), ctypes.c_void_p(sp) if want_S else None, where),
+            (L, S) if want_S else L)
         return (L, S) if want_S else L
 
     def momentum_project(self, L, mom):
@@ -405,7 +435,7 @@ class Lattice:
         self._stream_for(a)
         self._check(lib().fl_loops_grad(self._h, t_arr, nt, g_arr, ng, ctypes.c_void_p(a.ptr),
                                         ctypes.byref(params.c()), ctypes.c_void_p(dptr), ctypes.byref(dk),
-                                        a.where))
+                                        a.where), (dU, dk.value))
         return dU, dk.value
 
     def profile_enable(self, kernel=PROF_DSLASH, on=True):
@@ -433,7 +463,7 @@ class Lattice:
         (fl_set_tile) without timing, a miss times and adds its result."""
         key = None
         if cache is not None:
-            key = tune_key(_device_name(self.device), self.dims, prec, gauge_reals, nrhs)
+            key = tune_key(_device_name(self.device), self.dims, prec, gauge_reals, nrhs, version())
             hit = tune_cache_load(cache).get(key)
             if hit is not None:
                 self.set_tile(prec, gauge_reals, hit["rt"], hit["group"], hit["lds"])
@@ -454,9 +484,12 @@ def _device_name(device):
     return f"{p.name} {getattr(p, 'gcnArchName', '')}".strip()
 
 
-def tune_key(device_name, dims, prec, gauge_reals, nrhs):
-    """Key of one autotuner result."""
-    return f"{device_name}|{'x'.join(str(int(d)) for d in dims)}|prec{int(prec)}|r{int(gauge_reals)}|nrhs{int(nrhs)}"
+def tune_key(device_name, dims, prec, gauge_reals, nrhs, lib_version):
+    """Key of one autotuner result: the device, the lattice, the storage, the
+    right-hand sides and the library version (which names the hash of the
+    kernel sources, so a result timed on other kernels is not reused)."""
+    return (f"{device_name}|{'x'.join(str(int(d)) for d in dims)}|prec{int(prec)}|r{int(gauge_reals)}"
+            f"|nrhs{int(nrhs)}|{lib_version}")
 
 
 def tune_cache_load(path):
@@ -502,7 +535,8 @@ def loops_stochastic_multi(lattices, noises, gammas, lp: SolverParams = None, hp
     st = lib().fl_loops_stochastic_multi(hs, n, nps, g_arr, ng, ctypes.byref(lp.c()), ctypes.byref(hp.c()),
                                          parr, where)
     if st != 0:
-        raise FloopError(st, lib().fl_last_error(lattices[0]._h).decode())
+        # the thread's last error: also set by checks made before any context is used
+        raise FloopError(st, lib().fl_last_error(None).decode(), outs if st in (NOCONV, BREAKDOWN) else None)
     return outs
 
 

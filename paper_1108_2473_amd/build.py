@@ -25,11 +25,26 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+def source_hash() -> str:
+    """SHA-256 over the HIP sources, their headers and the C header, in sorted
+    path order (file name, then content): names the kernels a built library
+    and a recorded profile or tuning result belong to."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h")))
+    for f in files + [os.path.join(ROOT, "include", "floop.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     objdir = os.path.join(LIBDIR, "obj")
     os.makedirs(objdir, exist_ok=True)
-    flags = FLAGS
+    # the library reports the hash of the sources it was built from (fl_version)
+    flags = FLAGS + [f'-DFL_SRC_HASH="{source_hash()[:16]}"']
     procs, objs = [], []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")

@@ -2,6 +2,7 @@
 // drivers that turn the paper's loop estimators into batches of Schur
 // solves on the device.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -13,7 +14,11 @@ namespace {
 
 thread_local std::string g_last_error;
 
-const char *kVersion = "floop 0.1 (gfx950)";
+#ifndef FL_SRC_HASH
+#define FL_SRC_HASH "unknown"
+#endif
+// the hash names the kernel sources the library was built from
+const char *kVersion = "floop 0.2 (gfx950) src " FL_SRC_HASH;
 
 // Dirac matrices of the chiral basis, g_k = [[0, -i s_k], [i s_k, 0]],
 // g_4 = [[0, 1], [1, 0]], and products Gamma(mask) = g1^b0 g2^b1 g3^b2 g4^b3
@@ -99,7 +104,8 @@ fl_status check_params(fl_ctx *c, const fl_solver_params *p)
     if (p->inner_prec < FL_PREC_F64 || p->inner_prec > FL_PREC_H16)
         return set_err(c, FL_ERR_ARG, "unknown inner precision");
     if (p->gauge_reals != 18 && p->gauge_reals != 12) return set_err(c, FL_ERR_ARG, "gauge_reals must be 12 or 18");
-    if (p->max_iter < 0 || p->batch < 0) return set_err(c, FL_ERR_ARG, "negative max_iter or batch");
+    if (p->max_iter < 0 || p->batch < 0 || p->max_outer < 0)
+        return set_err(c, FL_ERR_ARG, "negative max_iter, batch or max_outer");
     if ((p->inner_prec == FL_PREC_BF16 || p->inner_prec == FL_PREC_H16) && p->gauge_reals != 12)
         return set_err(c, FL_ERR_ARG, "bfloat16 and 16-bit fixed-point links are stored with 12 reals");
     if (p->inner_prec != FL_PREC_F64 && p->gauge_reals == 12 && !c->su3)
@@ -172,6 +178,68 @@ fl_status norms64(fl_ctx *c, int nrhs, const void *fe, const void *fo, std::vect
     return FL_OK;
 }
 
+// |b - D x|^2 per right-hand side on the full operator in FP64 for n
+// right-hand sides of even/odd FP64 fields (x_o included), into r2 (host);
+// uses the workspace slots WS_HE and WS_HO
+fl_status full_residual2(fl_ctx *c, int n, const void *be, const void *bo, const void *xe, const void *xo,
+                         std::vector<double> &r2)
+{
+    const size_t fb = (size_t)n * c->Vh * 192;
+    void *he = ws_get(c, WS_HE, fb), *ho = ws_get(c, WS_HO, fb);
+    if (!he || !ho) return set_err(c, FL_ERR_NOMEM, "device allocation failed (residual check)");
+    // (D x)_e = x_e - k H_eo x_o, (D x)_o = x_o - k H_oe x_e
+    hop64(c, n, 0, xo, he, xe, 1.0, -c->kappa, false);
+    hop64(c, n, 1, xe, ho, xo, 1.0, -c->kappa, false);
+    fl_ctx *cs[1] = {c};
+    int nr[1] = {n};
+    BlasArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int RT, G;
+    tile_shape(c, LINK_F64_R18, n, &RT, &G);
+    a.B = batch_geom(cs, nr, 1, RT, G);
+    a.op = OP_SUB_HI;
+    a.nsys = n;
+    a.f[0][0] = he;
+    a.f[1][0] = (void *)be;
+    a.f[2][0] = he;
+    launch_blas(VEC_F64, a, c->stream);
+    a.f[0][0] = ho;
+    a.f[1][0] = (void *)bo;
+    a.f[2][0] = ho;
+    launch_blas(VEC_F64, a, c->stream);
+    return norms64(c, n, he, ho, r2);
+}
+
+// statistics of one solve, stored at index idx of the context's last-call list
+void put_stats(fl_ctx *c, size_t idx, const SysResult &r, bool truncated, double bnorm2, double r2, double tol,
+               double secs)
+{
+    if (c->last_stats.size() <= idx) c->last_stats.resize(idx + 1);
+    fl_solver_stats &s = c->last_stats[idx];
+    s.iters = r.iters;
+    s.updates = r.updates;
+    s.seconds = secs;
+    if (truncated) {
+        s.true_resid = r.true_resid;
+        s.converged = r.converged;
+    } else {
+        s.true_resid = bnorm2 > 0 ? std::sqrt(r2 / bnorm2) : std::sqrt(r2);
+        s.converged = s.true_resid <= tol ? 1 : 0;
+    }
+}
+
+// status of one solve from its statistics
+fl_status solve_status(const fl_solver_stats &s, const SysResult &r)
+{
+    if (s.converged) return FL_OK;
+    return (r.flags & ST_BREAK) ? FL_ERR_BREAKDOWN : FL_ERR_NOCONV;
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 // default right-hand sides per device batch: about `budget` bytes of vectors
 int default_batch(const fl_ctx *c, int multiple)
 {
@@ -203,8 +271,26 @@ fl_status set_err(fl_ctx *c, fl_status st, const std::string &msg)
     return st;
 }
 
+namespace {
+thread_local const char *g_launch_error = nullptr;
+}
+
+void launch_unsupported(const char *what)
+{
+    if (!g_launch_error) g_launch_error = what;
+}
+
+const char *take_launch_error()
+{
+    const char *w = g_launch_error;
+    g_launch_error = nullptr;
+    return w;
+}
+
 fl_status hip_check(fl_ctx *c, hipError_t e, const char *what)
 {
+    if (const char *le = take_launch_error())
+        return set_err(c, FL_ERR_ARG, std::string(what) + ": internal: kernel variant not built (" + le + ")");
     if (e == hipSuccess) return FL_OK;
     return set_err(c, e == hipErrorOutOfMemory ? FL_ERR_NOMEM : FL_ERR_DEVICE,
                    std::string(what) + ": " + hipGetErrorString(e));
@@ -374,6 +460,7 @@ void fl_solver_params_default(fl_solver_params *p)
     p->delta = 0.0;  // the solver picks its default for the inner precision
     p->truncated = 0;
     p->batch = 0;
+    p->max_outer = 0;
 }
 
 const char *fl_version(void) { return kVersion; }
@@ -587,7 +674,9 @@ fl_status fl_solve(fl_ctx *c, const double *b, double *x, int nrhs, const fl_sol
     const int chunk = std::max(1, std::min(nrhs, p->batch > 0 ? p->batch : default_batch(c, 1)));
     const size_t per = (size_t)c->V * 24 * sizeof(double);
     fl_status worst = FL_OK;
+    c->last_stats.assign(nrhs, fl_solver_stats{});
     for (int k0 = 0; k0 < nrhs; k0 += chunk) {
+        const double t_batch = now_s();
         int n = std::min(chunk, nrhs - k0);
         const double *src = b + (size_t)k0 * c->V * 24;
         double *dst = x + (size_t)k0 * c->V * 24;
@@ -603,8 +692,7 @@ fl_status fl_solve(fl_ctx *c, const double *b, double *x, int nrhs, const fl_sol
         size_t fb = (size_t)n * c->Vh * 192;
         void *be = ws_get(c, WS_BE, fb), *bo = ws_get(c, WS_BO, fb), *bh = ws_get(c, WS_BH, fb);
         void *xe = ws_get(c, WS_XE, fb), *xo = ws_get(c, WS_XO, fb);
-        void *he = ws_get(c, WS_HE, fb), *ho = ws_get(c, WS_HO, fb);
-        if (!be || !bo || !bh || !xe || !xo || !he || !ho) return set_err(c, FL_ERR_NOMEM, "device allocation failed");
+        if (!be || !bo || !bh || !xe || !xo) return set_err(c, FL_ERR_NOMEM, "device allocation failed");
         LatGeom g = lat_geom(c, n);
         launch_canon_to_eo(cin, (double2 *)be, (double2 *)bo, g, n, c->stream);
         std::vector<double> b2;
@@ -625,46 +713,22 @@ fl_status fl_solve(fl_ctx *c, const double *b, double *x, int nrhs, const fl_sol
         // x_o = b_o + k H_oe x_e
         hop64(c, n, 1, xe, xo, bo, 1.0, c->kappa, false);
         // stopping rule on the full operator: r = b - D x
-        hop64(c, n, 0, xo, he, xe, 1.0, -c->kappa, false);
-        hop64(c, n, 1, xe, ho, xo, 1.0, -c->kappa, false);
-        {
-            fl_ctx *cs[1] = {c};
-            int nr[1] = {n};
-            BlasArgs a;
-            std::memset(&a, 0, sizeof(a));
-            int RT, G;
-            tile_shape(c, LINK_F64_R18, n, &RT, &G);
-            a.B = batch_geom(cs, nr, 1, RT, G);
-            a.op = OP_SUB_HI;
-            a.nsys = n;
-            a.f[0][0] = he;
-            a.f[1][0] = be;
-            a.f[2][0] = he;
-            launch_blas(VEC_F64, a, c->stream);
-            a.f[0][0] = ho;
-            a.f[1][0] = bo;
-            a.f[2][0] = ho;
-            launch_blas(VEC_F64, a, c->stream);
-        }
         std::vector<double> r2;
-        if ((e = norms64(c, n, he, ho, r2))) return e;
+        if ((e = full_residual2(c, n, be, bo, xe, xo, r2))) return e;
         launch_eo_to_canon((double2 *)xe, (double2 *)xo, cout, g, n, c->stream);
         if (where == FL_HOST)
             if ((e = hip_check(c, hipMemcpyAsync(dst, cout, per * n, hipMemcpyDeviceToHost, c->stream), "download")))
                 return e;
         if ((e = hip_check(c, hipStreamSynchronize(c->stream), "solve"))) return e;
+        const double secs = now_s() - t_batch;
         for (int k = 0; k < n; ++k) {
-            double bn = sb.bnorm[k] > 0 ? sb.bnorm[k] : 1.0;
-            double tr = sb.bnorm[k] > 0 ? std::sqrt(r2[k]) / bn : 0.0;
-            bool conv = p->truncated ? res[k].converged != 0 : tr <= p->tol;
-            if (stats) {
-                fl_solver_stats &s = stats[k0 + k];
-                s.iters = res[k].iters;
-                s.updates = res[k].updates;
-                s.converged = conv ? 1 : 0;
-                s.true_resid = tr;
-            }
-            if (!conv && worst == FL_OK) worst = (res[k].flags & ST_BREAK) ? FL_ERR_BREAKDOWN : FL_ERR_NOCONV;
+            // truncated solves report the iteration's own residual; a zero
+            // source has the zero solution
+            put_stats(c, k0 + k, res[k], p->truncated != 0, b2[k], b2[k] > 0 ? r2[k] : 0.0, p->tol, secs);
+            const fl_solver_stats &s = c->last_stats[k0 + k];
+            if (stats) stats[k0 + k] = s;
+            fl_status q = solve_status(s, res[k]);
+            if (q != FL_OK && worst == FL_OK) worst = q;
         }
     }
     if (worst != FL_OK) return set_err(c, worst, "some right-hand sides did not reach tol");
@@ -701,13 +765,15 @@ fl_status fl_loops_exact_sites(fl_ctx *c, const long long *sites, long long nsit
                        "upload gammas")))
         return e;
     fl_status worst = FL_OK;
+    c->last_stats.assign((size_t)12 * nsites, fl_solver_stats{});
     for (long long s0 = 0; s0 < nsites; s0 += nsb) {
+        const double t_batch = now_s();
         int ns = (int)std::min<long long>(nsb, nsites - s0);
         int n = 12 * ns;
         size_t fb = (size_t)n * c->Vh * 192;
         void *be = ws_get(c, WS_BE, fb), *bo = ws_get(c, WS_BO, fb), *bh = ws_get(c, WS_BH, fb);
-        void *xe = ws_get(c, WS_XE, fb);
-        if (!be || !bo || !bh || !xe) return set_err(c, FL_ERR_NOMEM, "device allocation failed");
+        void *xe = ws_get(c, WS_XE, fb), *xo = ws_get(c, WS_XO, fb);
+        if (!be || !bo || !bh || !xe || !xo) return set_err(c, FL_ERR_NOMEM, "device allocation failed");
         LatGeom g = lat_geom(c, n);
         if ((e = hip_check(c, hipMemsetAsync(be, 0, fb, c->stream), "memset"))) return e;
         if ((e = hip_check(c, hipMemsetAsync(bo, 0, fb, c->stream), "memset"))) return e;
@@ -723,7 +789,16 @@ fl_status fl_loops_exact_sites(fl_ctx *c, const long long *sites, long long nsit
         std::vector<SysResult> res;
         fl_status se = solve_schur_batch(sb, *p, res);
         if (se != FL_OK && se != FL_ERR_NOCONV && se != FL_ERR_BREAKDOWN) return se;
-        if (se != FL_OK && worst == FL_OK) worst = se;
+        // acceptance on the full operator (point sources: |b| = 1)
+        hop64(c, n, 1, xe, xo, bo, 1.0, c->kappa, false);  // x_o = b_o + k H_oe x_e
+        std::vector<double> r2;
+        if ((e = full_residual2(c, n, be, bo, xe, xo, r2))) return e;
+        const double secs = now_s() - t_batch;
+        for (int k = 0; k < n; ++k) {
+            put_stats(c, (size_t)12 * s0 + k, res[k], p->truncated != 0, 1.0, r2[k], p->tol, secs);
+            fl_status q = solve_status(c->last_stats[(size_t)12 * s0 + k], res[k]);
+            if (q != FL_OK && worst == FL_OK) worst = q;
+        }
         ExactContractArgs a;
         a.g = g;
         a.nsites = ns;
@@ -768,8 +843,13 @@ fl_status fl_loops_stochastic_multi(fl_ctx **ctxs, int nctx, const fl_noise_para
                                     fl_where where)
 {
     if (!ctxs || nctx < 1 || nctx > FL_MAXLAT || !np || !Lout) return set_err(nullptr, FL_ERR_ARG, "bad lattice list");
-    for (int l = 0; l < nctx; ++l)
+    for (int l = 0; l < nctx; ++l) {
         if (!ctxs[l]) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
+        // a context holds one lattice's workspace: twice in one batch, the
+        // sources and Krylov vectors of one entry would overwrite the other's
+        for (int m = 0; m < l; ++m)
+            if (ctxs[m] == ctxs[l]) return set_err(nullptr, FL_ERR_ARG, "the same context appears twice in the batch");
+    }
     fl_ctx *c0 = ctxs[0];
     for (int l = 1; l < nctx; ++l)
         if (ctxs[l]->device != c0->device || ctxs[l]->stream != c0->stream)
@@ -860,6 +940,7 @@ fl_status fl_loops_stochastic_multi(fl_ctx **ctxs, int nctx, const fl_noise_para
     }
     // batches: all LP-type jobs, then all HP jobs; lattices advance together
     fl_status worst = FL_OK;
+    for (int l = 0; l < nctx; ++l) ctxs[l]->last_stats.assign(jobs[l].size(), fl_solver_stats{});
     for (int pass = 0; pass < 2; ++pass) {
         if (pass == 1 && !any_hp) break;
         const fl_solver_params &prm = pass ? *hp : *lp;
@@ -880,6 +961,7 @@ fl_status fl_loops_stochastic_multi(fl_ctx **ctxs, int nctx, const fl_noise_para
                 any |= nr[l] > 0;
             }
             if (!any) break;
+            const double t_batch = now_s();
             // every lattice takes part in the batch (possibly with no rhs)
             SolveBatch sb;
             sb.nlat = 0;
@@ -925,7 +1007,7 @@ fl_status fl_loops_stochastic_multi(fl_ctx **ctxs, int nctx, const fl_noise_para
             std::vector<SysResult> res;
             fl_status se = solve_schur_batch(sb, prm, res);
             if (se != FL_OK && se != FL_ERR_NOCONV && se != FL_ERR_BREAKDOWN) return se;
-            if (se != FL_OK && pass == 1 && worst == FL_OK) worst = se;
+            int sys0 = 0;
             for (int l = 0; l < nctx; ++l) {
                 fl_ctx *c = ctxs[l];
                 int n = nr[l];
@@ -935,6 +1017,19 @@ fl_status fl_loops_stochastic_multi(fl_ctx **ctxs, int nctx, const fl_noise_para
                 void *xo = ws_get(c, WS_XO, fb);
                 if (!xo) return set_err(c, FL_ERR_NOMEM, "device allocation failed");
                 hop64(c, n, 1, xe, xo, bo, 1.0, c->kappa, false);  // x_o = eta_o + k H_oe x_e
+                // statistics; solves that are not truncated are accepted on the
+                // full operator
+                std::vector<double> r2;
+                if (!prm.truncated && (e = full_residual2(c, n, be, bo, xe, xo, r2))) return e;
+                const double secs = now_s() - t_batch;
+                for (int k = 0; k < n; ++k) {
+                    const size_t job = (size_t)sel[l][pos[l] + k];
+                    const SysResult &r = res[sys0 + k];
+                    put_stats(c, job, r, prm.truncated != 0, bn[l][k], prm.truncated ? 0.0 : r2[k], prm.tol, secs);
+                    fl_status q = solve_status(c->last_stats[job], r);
+                    if (q != FL_OK && worst == FL_OK) worst = q;
+                }
+                sys0 += n;
                 StochContractArgs a;
                 a.g = lat_geom(c, n);
                 a.nrhs = n;
@@ -975,7 +1070,7 @@ fl_status fl_loops_stochastic_multi(fl_ctx **ctxs, int nctx, const fl_noise_para
             return e;
         if ((e = hip_check(c, hipStreamSynchronize(st), "sync"))) return e;
     }
-    if (worst != FL_OK) return set_err(c0, worst, "some high-precision solves did not reach tol");
+    if (worst != FL_OK) return set_err(c0, worst, "some solves did not reach their tolerance (fl_last_stats)");
     return FL_OK;
 }
 
@@ -1069,8 +1164,9 @@ fl_status fl_loops_grad(fl_ctx *c, const int *t0, int nt, const int *gammas, int
     const int batch = std::max(12, (p->batch > 0 ? p->batch : default_batch(c, 12)) / 12 * 12);
     const int nsb = batch / 12;
     fl_status worst = FL_OK;
-    std::vector<double> dpart(512);
+    c->last_stats.assign((size_t)12 * nsites, fl_solver_stats{});
     for (long long s0 = 0; s0 < nsites; s0 += nsb) {
+        const double t_batch = now_s();
         int ns = (int)std::min<long long>(nsb, nsites - s0);
         int n = 12 * ns;
         size_t fb = (size_t)n * c->Vh * 192;
@@ -1096,7 +1192,6 @@ fl_status fl_loops_grad(fl_ctx *c, const int *t0, int nt, const int *gammas, int
         std::vector<SysResult> res;
         fl_status se = solve_schur_batch(sb, *p, res);
         if (se != FL_OK && se != FL_ERR_NOCONV && se != FL_ERR_BREAKDOWN) return se;
-        if (se != FL_OK && worst == FL_OK) worst = se;
         hop64(c, n, 1, xe, xo, bo, 1.0, c->kappa, false);  // psi_o = b_o + k H_oe psi_e
         ChiArgs ca;
         ca.g = g;
@@ -1128,13 +1223,33 @@ fl_status fl_loops_grad(fl_ctx *c, const int *t0, int nt, const int *gammas, int
         fa.kappa = c->kappa;
         fa.dU = ddU;
         launch_force(fa, st);
+        // acceptance of the forward solves on the full operator (|b| = 1);
+        // the residual check reuses he, ho after the force kernel
+        std::vector<double> r2;
+        if ((e = full_residual2(c, n, be, bo, xe, xo, r2))) return e;
         if ((e = hip_check(c, hipStreamSynchronize(st), "gradient batch"))) return e;
         for (int k = 0; k < 256; ++k) dk += hp[2 * k] + hp[512 + 2 * k];
+        const double secs = now_s() - t_batch;
+        for (int k = 0; k < n; ++k) {
+            put_stats(c, (size_t)12 * s0 + k, res[k], p->truncated != 0, 1.0, r2[k], p->tol, secs);
+            fl_status q = solve_status(c->last_stats[(size_t)12 * s0 + k], res[k]);
+            if (q != FL_OK && worst == FL_OK) worst = q;
+        }
     }
     *dkappa = dk;
     if ((e = copy_out(c, dU, ddU, ub, where))) return e;
     if ((e = hip_check(c, hipStreamSynchronize(st), "gradient"))) return e;
     if (worst != FL_OK) return set_err(c, worst, "some point-source solves did not reach tol");
+    return FL_OK;
+}
+
+fl_status fl_last_stats(const fl_ctx *c, fl_solver_stats *stats, long long cap, long long *n)
+{
+    if (!c) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
+    if (!n || cap < 0 || (cap > 0 && !stats)) return set_err(const_cast<fl_ctx *>(c), FL_ERR_ARG, "bad output");
+    *n = (long long)c->last_stats.size();
+    const long long m = std::min<long long>(cap, *n);
+    for (long long k = 0; k < m; ++k) stats[k] = c->last_stats[(size_t)k];
     return FL_OK;
 }
 

@@ -234,7 +234,7 @@ void dispatch(const BlasArgs &a, dim3 grid, dim3 block, hipStream_t s)
     case OP_CG_PX: hipLaunchKernelGGL((k_blas<S, OP_CG_PX>), grid, block, 0, s, a); break;
     case OP_DOT: hipLaunchKernelGGL((k_blas<S, OP_DOT>), grid, block, 0, s, a); break;
     case OP_CG_FIXP: hipLaunchKernelGGL((k_blas<S, OP_CG_FIXP>), grid, block, 0, s, a); break;
-    default: break;
+    default: launch_unsupported("vector operation"); break;
     }
 }
 
@@ -462,5 +462,9 @@ void launch_blas(VecFormat vf, const BlasArgs &a, hipStream_t s)
 void launch_scalars(const ScalArgs &a, hipStream_t s)
 {
     if (a.nsys == 0) return;
+    if (a.step < SC_ALPHA || a.step > SC_CG_REZ) {
+        launch_unsupported("scalar step");
+        return;
+    }
     hipLaunchKernelGGL(k_scal, dim3(a.nsys), dim3(256), 0, s, a);
 }

@@ -410,8 +410,10 @@ void dispatch_epi(const DslashArgs &a, int epi, dim3 grid, dim3 block, hipStream
     case EPI_XPAY | EPI_NORM | EPI_SUBY16:
         if constexpr (std::is_same<S, double>::value)
             launch_one<S, LK, DAG, EPI_XPAY | EPI_NORM | EPI_SUBY16>(a, grid, block, s);
+        else
+            launch_unsupported("hopping epilogue: 16-bit subtraction needs FP64 fields");
         break;
-    default: break;
+    default: launch_unsupported("hopping epilogue"); break;
     }
 }
 
@@ -459,12 +461,16 @@ void launch_dslash(LinkFormat fmt, const DslashArgs &a, bool dag, int epi, hipSt
 {
     dim3 grid(a.B.ntiles), block(FL_WAVE * a.B.RT);
     if (a.B.ntiles == 0) return;
+    if (!dslash_epi_supported(epi)) {
+        launch_unsupported("hopping epilogue");
+        return;
+    }
     switch (fmt) {
     case LINK_F64_R18: dispatch_dag<double, LinkF64R18>(a, dag, epi, grid, block, s); break;
     case LINK_F32_R18: dispatch_dag<float, LinkF32R18>(a, dag, epi, grid, block, s); break;
     case LINK_F32_R12: dispatch_dag<float, LinkF32R12>(a, dag, epi, grid, block, s); break;
     case LINK_BF16_R12: dispatch_dag<float, LinkBF16R12>(a, dag, epi, grid, block, s); break;
     case LINK_Q16_R12: dispatch_dag<H16, LinkQ16R12>(a, dag, epi, grid, block, s); break;
-    default: break;
+    default: launch_unsupported("hopping link format"); break;
     }
 }

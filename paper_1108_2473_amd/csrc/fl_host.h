@@ -60,6 +60,11 @@ struct DslashArgs {
 };
 
 bool dslash_epi_supported(int epi);
+// A dispatcher asked for a kernel variant that is not built records it here
+// instead of launching nothing silently; hip_check() turns it into
+// FL_ERR_ARG at the caller's next check of the stream.
+void launch_unsupported(const char *what);
+const char *take_launch_error();
 // LDS bytes the staged kernel needs for RT right-hand sides
 size_t dslash_lds_bytes(LinkFormat fmt, int RT, int wsmax, int lds);
 void launch_dslash(LinkFormat fmt, const DslashArgs &a, bool dag, int epi, hipStream_t s);
@@ -264,6 +269,7 @@ struct fl_ctx {
     int tune_g[LINK_NFMT] = {};
     int tune_lds[LINK_NFMT] = {-1, -1, -1, -1, -1};  // LDS staging mode; -1: built-in choice
     size_t max_lds = 65536;              // LDS bytes a workgroup may use on this device
+    std::vector<fl_solver_stats> last_stats;  // per-solve statistics of the last solving call
 };
 
 // LDS staging mode and window length for a hopping launch over batch B

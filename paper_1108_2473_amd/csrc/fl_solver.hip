@@ -513,12 +513,13 @@ fl_status Solver::run(std::vector<SysResult> &res)
                 res[k].updates++;
                 const SysState &s = hst[k];
                 bool ok = s.tr2 <= s.tstop2;
-                if (ok || final_upd[k] || s.iter >= s.max_iter) {
+                const bool out_of_cycles = prm.max_outer > 0 && res[k].updates >= prm.max_outer;
+                if (ok || final_upd[k] || s.iter >= s.max_iter || out_of_cycles) {
                     done[k] = 1;
                     ++ndone;
                     hact[k] = 0;
                     res[k].converged = ok ? 1 : 0;
-                    res[k].flags = s.flags | (final_upd[k] ? ST_MAXIT : 0);
+                    res[k].flags = s.flags | ((final_upd[k] || (!ok && out_of_cycles)) ? ST_MAXIT : 0);
                 } else {
                     hact[k] = 1;
                 }

@@ -106,6 +106,20 @@ def random_spinors(dims, nrhs, seed):
     return np.ascontiguousarray(z[..., 0] + 1j * z[..., 1])
 
 
+def z4_diluted_sources(dims, comps, seed):
+    """Sources [n][V][4][3] with Z4 values {1, i, -1, -i} drawn from PCG64(seed)
+    on one timeslice, spin and colour each (comps = [(t, spin, colour), ...]):
+    the shape and value distribution of spin-colour-time diluted Z4 noise, for
+    inputs that both sides receive as given arrays."""
+    V = volume(dims)
+    Vs = dims[0] * dims[1] * dims[2]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.zeros((len(comps), V, 4, 3), dtype=np.complex128)
+    for k, (t, spin, col) in enumerate(comps):
+        out[k, Vs * t:Vs * (t + 1), spin, col] = 1j ** rng.integers(0, 4, Vs)
+    return out
+
+
 def site_index(dims, x, y, z, t):
     return x + dims[0] * (y + dims[1] * (z + dims[2] * t))
 

@@ -6,10 +6,19 @@ import paper_1108_2473_amd as fl
 
 
 def test_key_names_every_field():
-    k = fl.tune_key("AMD Instinct MI355X gfx950", (16, 16, 16, 32), fl.PREC_H16, 12, 384)
-    assert k == "AMD Instinct MI355X gfx950|16x16x16x32|prec3|r12|nrhs384"
-    assert k != fl.tune_key("AMD Instinct MI355X gfx950", (16, 16, 16, 32), fl.PREC_F32, 12, 384)
-    assert k != fl.tune_key("other", (16, 16, 16, 32), fl.PREC_H16, 12, 384)
+    v = "floop 0.2 (gfx950) src 0123456789abcdef"
+    k = fl.tune_key("AMD Instinct MI355X gfx950", (16, 16, 16, 32), fl.PREC_H16, 12, 384, v)
+    assert k == "AMD Instinct MI355X gfx950|16x16x16x32|prec3|r12|nrhs384|" + v
+    assert k != fl.tune_key("AMD Instinct MI355X gfx950", (16, 16, 16, 32), fl.PREC_F32, 12, 384, v)
+    assert k != fl.tune_key("other", (16, 16, 16, 32), fl.PREC_H16, 12, 384, v)
+    # a library built from other kernel sources does not reuse the result
+    assert k != fl.tune_key("AMD Instinct MI355X gfx950", (16, 16, 16, 32), fl.PREC_H16, 12, 384,
+                            "floop 0.2 (gfx950) src fedcba9876543210")
+
+
+def test_library_version_names_its_kernel_sources():
+    from paper_1108_2473_amd import build
+    assert fl.version().endswith("src " + build.source_hash()[:16])
 
 
 def test_store_and_load_round_trip(tmp_path):

@@ -64,3 +64,28 @@ def test_library_is_built_for_gfx950_only():
     from paper_1108_2473_amd import build
     src = open(build.__file__).read()
     assert 'ARCH = "gfx950"' in src and "-packed-fp32-ops" in src
+
+
+def test_batched_loops_reject_a_context_given_twice(lib):
+    """fl_loops_stochastic_multi compares the context pointers before using
+    them: the same context twice would share one workspace (no GPU work and
+    no dereference happens; the pointers here are placeholders)."""
+    import paper_1108_2473_amd as fl
+    dummy = ctypes.create_string_buffer(64)
+    h = ctypes.cast(dummy, ctypes.c_void_p).value
+    hs = (ctypes.c_void_p * 2)(h, h)
+    nps = (fl._NoiseParams * 2)()
+    g = (ctypes.c_int * 1)(0)
+    outs = (ctypes.c_void_p * 2)(h, h)
+    p = fl._SolverParams()
+    lib.fl_solver_params_default(ctypes.byref(p))
+    st = lib.fl_loops_stochastic_multi(hs, 2, nps, g, 1, ctypes.byref(p), ctypes.byref(p), outs, 0)
+    assert st == -1
+    assert b"twice" in lib.fl_last_error(None)
+    assert dummy.raw == b"\0" * 64  # the placeholder was not written
+
+
+def test_last_stats_argument_checks(lib):
+    n = ctypes.c_longlong(-7)
+    assert lib.fl_last_stats(None, None, 0, ctypes.byref(n)) == -1
+    assert n.value == -7
