@@ -199,6 +199,20 @@ fl_status fl_set_kappa(fl_ctx *ctx, double kappa);
 fl_status fl_apply_D(fl_ctx *ctx, const double *in, double *out, int nrhs, int dagger,
                      fl_where where);
 
+/* fl_apply_D for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): in
+ * and out are DEVICE pointers (canonical layout, FP64, nrhs spinors), and
+ * the even/odd work fields live in a fixed device array of the library
+ * (64 MiB per GPU, held until the process ends), so nrhs * V * 384 bytes
+ * may not exceed 64 MiB (16^3 x 32: one spinor); larger requests return
+ * FL_ERR_ARG.  Calls no hipMalloc, hipFree or allocating routine and does
+ * not synchronise: the work is enqueued on the context stream and the call
+ * returns (synchronise the stream before reading out).  The array is shared
+ * by every call on one GPU, so calls that overlap on one GPU (other streams,
+ * other host threads) race; nothing in it needs to start at zero.
+ * FL_ERR_STATE before fl_set_gauge / fl_set_kappa. */
+fl_status fl_apply_D_noalloc(fl_ctx *ctx, const double *in, double *out, int nrhs, int dagger);
+
 /* The even-odd Schur operator Dhat = 1 - kappa^2 H_eo H_oe (dagger = 1:
  * Dhat^+ = g5 Dhat g5) as the solvers apply it, in the iteration precision
  * and link storage of p (inner_prec, gauge_reals; p->batch bounds the

@@ -409,3 +409,56 @@ def dilution_study(configs, dims, bc_t, kappa, n_noise, schemes, tsm, seed, tol_
     out["stochastic"] = {k: np.array(v) for k, v in out["stochastic"].items()}
     out["tsm"] = {k: np.array(v) for k, v in out["tsm"].items()}
     return out
+
+
+# ---------------------------------------------------------------------------
+# the paper's comparison per insertion (Sec. IV, figures "spin gammas" and
+# "truncated gammas"; Sec. V, figure "compare_unity"): momentum-projected
+# loops of each (Gamma, p) estimated stochastically against the exact ones
+# ---------------------------------------------------------------------------
+GAMMA_MOMENTA = ((1, (1, 0, 0)), (2, (0, 1, 0)), (4, (0, 0, 1)), (8, (1, 0, 0)), (0, (0, 0, 0)))
+
+
+def loop_error_study(configs, dims, bc_t, kappa, n_noise, schemes, tsm, seed, tol_hp, tol_lp, tol_exact=1e-13,
+                     pairs=GAMMA_MOMENTA, tsm_dilution=0, with_exact=True):
+    """Lp_Gamma(p, t) = sum_x exp(i p.x) L_Gamma(x, t) on all timeslices for
+    each (Gamma, p) in `pairs` (default: g1 at p = (1,0,0), g2 at (0,1,0), g3 at
+    (0,0,1), g4 at (1,0,0), as in the paper's nucleon three-point ratios, and
+    the scalar at p = 0), per configuration:
+      exact              loops from point sources on every site,
+      stochastic         for each dilution mask of `schemes` (name -> mask) and
+                         each N of n_noise, the mean of the loops of the first N
+                         complex Z2 noise vectors (Eq. loop stochastic),
+      tsm                for each (n_lp, n_hp), the truncated-solver estimate
+                         (LP solves truncated at tol_lp, HP at tol_hp) with
+                         noise seed + 1, diluted with `tsm_dilution`.
+    Configuration c uses noise seed + 1000 c.  Returns dicts of arrays
+    [nconf][npairs][T] (exact None when with_exact is False)."""
+    T = dims[3]
+    gam = sorted({g for g, _ in pairs})
+    moms = sorted({tuple(m) for _, m in pairs})
+    gi = {g: k for k, g in enumerate(gam)}
+    mi = {m: k for k, m in enumerate(moms)}
+
+    def project(L):  # [ngam][T][Vs] -> [npairs][T]
+        P = momentum_project(L, dims, moms)
+        return np.array([P[gi[g], mi[tuple(m)]] for g, m in pairs])
+
+    out = {"exact": [], "stochastic": {}, "tsm": {}}
+    for ci, U in enumerate(configs):
+        cseed = seed + 1000 * ci
+        if with_exact:
+            out["exact"].append(project(loops_exact(U, dims, bc_t, kappa, list(range(T)), gam, tol=tol_exact)))
+        for name, mask in schemes.items():
+            per = [project(loops_stochastic(U, dims, bc_t, kappa, NOISE_CZ2, cseed, r, 1, mask, 0, T, gam,
+                                            tol=tol_hp)) for r in range(max(n_noise))]
+            for N in n_noise:
+                out["stochastic"].setdefault((name, N), []).append(np.mean(per[:N], axis=0))
+        for (n_lp, n_hp) in tsm:
+            out["tsm"].setdefault((n_lp, n_hp), []).append(
+                project(loops_tsm(U, dims, bc_t, kappa, NOISE_CZ2, cseed + 1, 0, n_lp, n_hp, tol_lp, tol_hp,
+                                  tsm_dilution, 0, T, gam)))
+    out["exact"] = np.array(out["exact"]) if with_exact else None
+    out["stochastic"] = {k: np.array(v) for k, v in out["stochastic"].items()}
+    out["tsm"] = {k: np.array(v) for k, v in out["tsm"].items()}
+    return out

@@ -128,6 +128,7 @@ def lib():
     L.fl_set_gauge.argtypes = [vp, vp, i]
     L.fl_set_kappa.argtypes = [vp, d]
     L.fl_apply_D.argtypes = [vp, vp, vp, i, i, i]
+    L.fl_apply_D_noalloc.argtypes = [vp, vp, vp, i, i]
     L.fl_apply_schur.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(_SolverParams), i]
     L.fl_solve.argtypes = [vp, vp, vp, i, ctypes.POINTER(_SolverParams), ctypes.POINTER(_SolverStats), i]
     L.fl_loops_exact.argtypes = [vp, ctypes.POINTER(i), i, ctypes.POINTER(i), i,
@@ -157,7 +158,7 @@ def lib():
                  "fl_apply_schur", "fl_solve", "fl_loops_exact", "fl_loops_exact_sites", "fl_loops_stochastic",
                  "fl_loops_stochastic_multi", "fl_loops_grad", "fl_profile_enable", "fl_profile_read",
                  "fl_bench_dslash", "fl_set_tile", "fl_autotune", "fl_momentum_project", "fl_disconnected_corr", "fl_smear",
-                 "fl_pion_corr", "fl_last_stats"):
+                 "fl_pion_corr", "fl_last_stats", "fl_apply_D_noalloc"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -278,6 +279,21 @@ class Lattice:
         self._stream_for(a)
         self._check(lib().fl_apply_D(self._h, ctypes.c_void_p(a.ptr), ctypes.c_void_p(optr), nrhs,
                                      int(dagger), a.where))
+        return out
+
+    def apply_D_noalloc(self, psi, out, dagger=False):
+        """out = D psi (fl_apply_D_noalloc) for torch complex128 CUDA tensors
+        psi and out of shape (..., V, 4, 3): no device allocation inside the
+        library; enqueued on torch's current stream, not synchronised."""
+        a, nrhs = self._spinors(psi)
+        o, n2 = self._spinors(out)
+        if not (a.torch and o.torch) or a.shape != o.shape:
+            raise ValueError("apply_D_noalloc takes two CUDA tensors of the same shape")
+        if o.obj is not out:
+            raise ValueError("out must be a contiguous complex128 tensor")
+        self._stream_for(a)
+        self._check(lib().fl_apply_D_noalloc(self._h, ctypes.c_void_p(a.ptr), ctypes.c_void_p(o.ptr), nrhs,
+                                             int(dagger)))
         return out
 
     def apply_schur(self, psi, params: SolverParams = None, dagger=False):

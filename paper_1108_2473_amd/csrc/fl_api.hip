@@ -10,6 +10,29 @@
 
 #include "fl_host.h"
 
+void hop64_launch(fl_ctx *c, const void *gauge, int nrhs, int par, const void *in, void *out, const void *x,
+                  double ca, double cb, bool dag, int epi)
+{
+    int RT, G;
+    tile_shape(c, LINK_F64_R18, nrhs, &RT, &G);
+    fl_ctx *cs[1] = {c};
+    int nr[1] = {nrhs};
+    DslashArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.B = batch_geom(cs, nr, 1, RT, G);
+    a.par = par;
+    a.nsys = nrhs;
+    a.in[0] = in;
+    a.out[0] = out;
+    a.x[0] = x;
+    a.gauge[0] = gauge;
+    a.ca[0] = ca;
+    a.cb[0] = cb;
+    if (epi < 0) epi = x ? EPI_XPAY : EPI_PLAIN;
+    dslash_config(c, LINK_F64_R18, a);
+    launch_dslash(LINK_F64_R18, a, dag, epi, c->stream);
+}
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -117,24 +140,7 @@ fl_status check_params(fl_ctx *c, const fl_solver_params *p)
 void hop64(fl_ctx *c, int nrhs, int par, const void *in, void *out, const void *x, double ca, double cb, bool dag,
            int epi = -1)
 {
-    int RT, G;
-    tile_shape(c, LINK_F64_R18, nrhs, &RT, &G);
-    fl_ctx *cs[1] = {c};
-    int nr[1] = {nrhs};
-    DslashArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.B = batch_geom(cs, nr, 1, RT, G);
-    a.par = par;
-    a.nsys = nrhs;
-    a.in[0] = in;
-    a.out[0] = out;
-    a.x[0] = x;
-    a.gauge[0] = links(c, LINK_F64_R18);
-    a.ca[0] = ca;
-    a.cb[0] = cb;
-    if (epi < 0) epi = x ? EPI_XPAY : EPI_PLAIN;
-    dslash_config(c, LINK_F64_R18, a);
-    launch_dslash(LINK_F64_R18, a, dag, epi, c->stream);
+    hop64_launch(c, links(c, LINK_F64_R18), nrhs, par, in, out, x, ca, cb, dag, epi);
 }
 
 // |f|^2 per right-hand side of FP64 (even, odd) fields, summed on the host in
@@ -501,6 +507,9 @@ fl_status fl_create(fl_ctx **out, int device, const int dims[4], int bc_t)
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->max_lds = (size_t)lds;
+    // device address of the fixed scratch array of fl_apply_D_noalloc on this
+    // device (once per device; a failure is reported by that entry point)
+    (void)noalloc_scratch_setup(device);
     *out = c;
     return FL_OK;
 }

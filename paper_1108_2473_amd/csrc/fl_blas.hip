@@ -355,8 +355,16 @@ __device__ __forceinline__ void scal_step(const ScalArgs &a, const double P[6], 
             s.alpha[0] = s.zz / P[2];
         }
         break;
-    case SC_CG_BETA: {  // slot 2: |z'|^2, slot 5: |r|^2
-        double zn = P[2], rr = P[5];
+    case SC_CG_BETA: {  // slot 2: |z'|^2 of the updated z = Dhat^+ r; slot 5: |r|^2 if carried
+        // Without a carried r: |r - alpha q|^2 = |r|^2 - 2 alpha Re<q, r>
+        // + alpha^2 |q|^2 with <q, r> = <p, Dhat^+ r> = <p, z> = |z|^2 (CG;
+        // restored at every residual replacement) and alpha = |z|^2 / |q|^2.
+        // The recurrence holds to the rounding of the low-precision operator
+        // relative to |r|^2 at the last replacement, so below 1e-6 of that
+        // value it is no longer trusted: it still asks for a replacement
+        // (far below the delta trigger) but claims no convergence
+        double zn = P[2], rr = a.carried_r ? P[5] : s.rr - s.alpha[0] * s.zz;
+        const bool trusted = a.carried_r || rr > 1e-6 * s.rmax2;
         s.xstamp = a.stamp;  // r moved by alpha q in this iteration: x moves by alpha p
         s.iter += 1;
         s.rr = rr;
@@ -368,8 +376,8 @@ __device__ __forceinline__ void scal_step(const ScalArgs &a, const double P[6], 
         s.beta[0] = zn / s.zz;
         s.zz = zn;
         if (rr > s.rmax2) s.rmax2 = rr;
-        if (rr < s.delta2 * s.rmax2) s.flags |= ST_WANT_UPD;
-        if (rr <= s.stop2) {
+        if (rr < s.delta2 * s.rmax2 || !trusted) s.flags |= ST_WANT_UPD;
+        if (trusted && rr <= s.stop2) {
             s.flags |= ST_CONV_ITER;
             act = 0;
         } else if (s.iter >= s.max_iter) {

@@ -58,6 +58,14 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
 #pragma unroll
         for (int k = 0; k < 12; ++k) out[k] = cb * acc[k];
     }
+    if constexpr ((EPI & EPI_CGZ) != 0) {
+        // out = y - alpha (x + cb acc), y the field this launch overwrites (own site only)
+        cx<R> yv[12];
+        F::load(spinor_buf<S>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, yv);
+        const R al = (R)a.st[T.sys].alpha[0];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) out[k] = cx<R>{fma(-al, out[k].re, yv[k].re), fma(-al, out[k].im, yv[k].im)};
+    }
     if constexpr ((EPI & EPI_SUBY16) != 0 && std::is_same<S, double>::value) {
         cx<float> y16[12];
         SpinorFmt<H16>::load(spinor_buf<H16>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, y16);
@@ -407,6 +415,7 @@ void dispatch_epi(const DslashArgs &a, int epi, dim3 grid, dim3 block, hipStream
     case EPI_XPAY | EPI_DOTY: launch_one<S, LK, DAG, EPI_XPAY | EPI_DOTY>(a, grid, block, s); break;
     case EPI_XPAY | EPI_DOTX_NORM: launch_one<S, LK, DAG, EPI_XPAY | EPI_DOTX_NORM>(a, grid, block, s); break;
     case EPI_NORM: launch_one<S, LK, DAG, EPI_NORM>(a, grid, block, s); break;
+    case EPI_XPAY | EPI_NORM | EPI_CGZ: launch_one<S, LK, DAG, EPI_XPAY | EPI_NORM | EPI_CGZ>(a, grid, block, s); break;
     case EPI_XPAY | EPI_NORM | EPI_SUBY16:
         if constexpr (std::is_same<S, double>::value)
             launch_one<S, LK, DAG, EPI_XPAY | EPI_NORM | EPI_SUBY16>(a, grid, block, s);
@@ -444,7 +453,7 @@ bool dslash_epi_supported(int epi)
 {
     return epi == EPI_PLAIN || epi == EPI_XPAY || epi == (EPI_XPAY | EPI_NORM) ||
            epi == (EPI_XPAY | EPI_DOTY) || epi == (EPI_XPAY | EPI_DOTX_NORM) || epi == EPI_NORM ||
-           epi == (EPI_XPAY | EPI_NORM | EPI_SUBY16);
+           epi == (EPI_XPAY | EPI_NORM | EPI_SUBY16) || epi == (EPI_XPAY | EPI_NORM | EPI_CGZ);
 }
 
 void launch_dslash_h16_wide(const DslashArgs &a, bool dag, hipStream_t s)

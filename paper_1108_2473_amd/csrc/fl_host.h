@@ -38,8 +38,12 @@ enum {
     EPI_DOTY = 2,       // partial slots slot0, slot0+1: <y, out>
     EPI_DOTX_NORM = 4,  // slots slot0, slot0+1: <out, x>; slot0+2: |out|^2
     EPI_NORM = 8,       // slot0+2: |out|^2
-    EPI_SUBY16 = 16     // FP64 fields only: out -= y, y a 16-bit field (its decoded values)
+    EPI_SUBY16 = 16,    // FP64 fields only: out -= y, y a 16-bit field (its decoded values)
+    EPI_CGZ = 32        // with EPI_XPAY: out = y - alpha (ca x + cb H in), alpha = st[sys].alpha[0]
+                        // (CGNR: z -= alpha Dhat^+ q, y = z updated in place)
 };
+
+struct SysState;
 
 struct DslashArgs {
     BatchGeom B;
@@ -57,6 +61,7 @@ struct DslashArgs {
     int lds;    // 0: neighbours from memory; 1: x/y neighbours from an LDS window;
                 // 2: also the workgroup's links staged in LDS once
     int wsmax;  // LDS window length in sites (64 + 2 * max Lx/2), set by the launcher
+    const SysState *st;  // per-system scalars (EPI_CGZ)
 };
 
 bool dslash_epi_supported(int epi);
@@ -103,7 +108,7 @@ enum BlasOp {
     OP_SUB_HI,        // f0 out (FP64) = f1 - f2 (FP64)
     OP_NORM,          // |f0|^2 -> slot0+2
     OP_ZERO,          // f0 = 0
-    OP_CG_R,          // CGNR: f0 r -= a q (f1 q), |r|^2; real a = zz/qq
+    OP_CG_R,          // CGNR (truncated solves): f0 r -= a q (f1 q), |r|^2; real a = zz/qq
     OP_CG_P,          // CGNR: f0 p = f1 z + beta p
     OP_CG_PX,         // CGNR: f2 x += a p where the state carries this launch's stamp, then
                       //       f0 p = f1 z + beta p for the masked (active) systems
@@ -139,6 +144,7 @@ struct ScalArgs {
     const double *partial;
     SysState *st;
     int stamp;  // iteration stamp, recorded by SC_CG_BETA
+    int carried_r;  // SC_CG_BETA: |r|^2 of a carried residual in slot 5 (else the scalar recurrence)
 };
 void launch_scalars(const ScalArgs &a, hipStream_t s);
 
@@ -286,6 +292,15 @@ BatchGeom batch_geom(fl_ctx *const *ctx, const int *nrhs, int nlat, int RT, int 
 // right-hand sides: RT waves (right-hand sides) per workgroup and G
 // right-hand-side blocks per site sweep (the autotuner's choice if any)
 void tile_shape(const fl_ctx *c, int fmt, int nrhs, int *RT, int *G);
+// single-lattice hopping launch on FP64 fields with the given FP64 links:
+// out = ca x + cb H in (x may be null: out = cb H in); epi < 0: XPAY if x
+void hop64_launch(fl_ctx *c, const void *gauge, int nrhs, int par, const void *in, void *out, const void *x,
+                  double ca, double cb, bool dag, int epi = -1);
+// size of the fixed device scratch array of fl_apply_D_noalloc (MiB)
+#define FL_NOALLOC_SCRATCH_MB 64
+// takes the device address of that array on `device` (once; call with the
+// device current)
+hipError_t noalloc_scratch_setup(int device);
 // kernel profiling hooks (events on the context stream)
 void prof_begin(fl_ctx *c, int kernel);
 void prof_end(fl_ctx *c, int kernel, double bytes);

@@ -65,6 +65,7 @@ struct Solver {
         a.nsys = nsys;
         a.mask = msk;
         a.partial = partial;
+        a.st = dst;
         for (int l = 0; l < B.nlat; ++l) {
             a.in[l] = in.p[l];
             a.out[l] = out.p[l];
@@ -112,6 +113,7 @@ struct Solver {
         a.partial = partial;
         a.st = dst;
         a.stamp = stamp;
+        a.carried_r = prm.truncated != 0;
         launch_scalars(a, st);
     }
 
@@ -138,7 +140,13 @@ struct Solver {
         blas(lf, OP_BICG_P, {&P, &R, &V}, 0, 0, active);          // p = r + beta (p - omega v)
     }
 
-    // CGNR on the Schur system: p, q = Dhat p, z = Dhat^+ r
+    // CGNR on the Schur system: p, q = Dhat p and the normal residual
+    // z = Dhat^+ r.  Solves accepted on the FP64 residual carry z itself,
+    // z -= alpha Dhat^+ q, fused into the epilogue of the second hop of
+    // Dhat^+ (the residual r = b - Dhat x is formed only at a replacement;
+    // |r|^2 follows from the scalars): one vector pass of r -= alpha q (three
+    // fields) fewer per iteration.  Truncated solves, which stop on their
+    // own residual with no FP64 check, carry r and form z = Dhat^+ r.
     void cg_iteration()
     {
         const VecFormat lf = vf;
@@ -147,10 +155,17 @@ struct Solver {
         dslash(fmt, true, 1, P, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, false, true);
         dslash(fmt, true, 0, TMP, V, &P, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, false, false);
         scal(SC_CG_ALPHA, nullptr);
-        blas(lf, OP_CG_R, {&R, &V}, 0, 3, active);                // r -= alpha q, |r|^2 -> slot 5
-        // z = Dhat^+ r with |z|^2 (slot 2)
-        dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, true, false);
-        dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, true, false);
+        if (prm.truncated) {
+            blas(lf, OP_CG_R, {&R, &V}, 0, 3, active);  // r -= alpha q, |r|^2 -> slot 5
+            // z = Dhat^+ r with |z|^2 (slot 2)
+            dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, true, false);
+            dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, true, false);
+        } else {
+            // z -= alpha Dhat^+ q in the epilogue of the second hop, with |z|^2 (slot 2)
+            dslash(fmt, true, 1, V, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, true, false);
+            dslash(fmt, true, 0, TMP, S, &V, &S, 1.0, neg_k2, EPI_XPAY | EPI_NORM | EPI_CGZ, 0, active, true,
+                   false);
+        }
         scal(SC_CG_BETA, nullptr);
         // x += alpha p (also for a system that stopped in SC_CG_BETA), then p = z + beta p
         blas(lf, OP_CG_PX, {&P, &S, &XL}, 0, 0, active);
@@ -311,7 +326,11 @@ fl_status Solver::run(std::vector<SysResult> &res)
         SysState &s = hst[k];
         std::memset(&s, 0, sizeof(s));
         double bn = sb.bnorm[k];
-        s.tstop2 = (tol * bn) * (tol * bn);
+        // accepted 1 % below tol: the callers recompute the residual on the
+        // full operator after the solve, and that FP64 recomputation differs
+        // from the Schur residual by rounding (~1e-4 of tol |b| at 16^3x32)
+        const double acc = trunc ? tol : 0.99 * tol;
+        s.tstop2 = (acc * bn) * (acc * bn);
         // the iteration aims a little below the target so that the FP64 check passes
         s.stop2 = trunc ? s.tstop2 : 0.25 * s.tstop2;
         s.delta2 = (lo64 || trunc) ? 0.0 : delta * delta;
@@ -424,12 +443,15 @@ fl_status Solver::run(std::vector<SysResult> &res)
         account_prof();
 
         if (solver == FL_SOLVER_CGNR && !trunc && any_active) {
-            // per-iteration factor of the recursive |r|^2 of the fastest system
-            // that iterated the whole chunk; next chunk ~ log(delta^2) / log(factor)
+            // per-iteration factor of |r|^2 of the fastest system that iterated
+            // the whole chunk, where its estimate is trusted (the scalar
+            // recurrence above 1e-6 of its value at the last replacement);
+            // next chunk ~ log(delta^2) / log(factor)
             double fmin = 1.0;
             const int nch = chunk;
             for (int k = 0; k < nsys; ++k)
-                if (act_start[k] && hact[k] && !done[k] && rr_prev[k] > 0 && hst[k].rr > 0 && hst[k].rr < rr_prev[k])
+                if (act_start[k] && hact[k] && !done[k] && rr_prev[k] > 0 && hst[k].rr > 1e-6 * hst[k].rmax2 &&
+                    hst[k].rr < rr_prev[k])
                     fmin = std::min(fmin, std::pow(hst[k].rr / rr_prev[k], 1.0 / nch));
             if (fmin < 1.0)
                 chunk = std::min(16, std::max(2, (int)std::floor(std::log(delta * delta) / std::log(fmin))));

@@ -109,6 +109,96 @@ def table(res: StudyResult, t=3):
     return rows
 
 
+# ---------------------------------------------------------------------------
+# the comparison per insertion (Sec. IV, figures "spin gammas" and "truncated
+# gammas"; Sec. V, figure "compare_unity"): momentum-projected loops
+# Lp_Gamma(p, t) = sum_x exp(i p.x) L_Gamma(x, t) of g1..g4 at the lowest
+# momenta of the paper's three-point ratios and of the scalar at p = 0,
+# stochastic and truncated-solver estimates against the exact loops
+# ---------------------------------------------------------------------------
+GAMMA_MOMENTA = ((1, (1, 0, 0)), (2, (0, 1, 0)), (4, (0, 0, 1)), (8, (1, 0, 0)), (0, (0, 0, 0)))
+PAIR_NAMES = {1: "g1", 2: "g2", 4: "g3", 8: "g4", 0: "1", 15: "g5"}
+
+
+@dataclass
+class LoopStudyResult:
+    """Per-configuration projected loops [nconf][npairs][T] for every estimator."""
+    T: int
+    pairs: tuple
+    exact: np.ndarray = None
+    stochastic: dict = field(default_factory=dict)  # (scheme, N) -> [nconf][npairs][T]
+    tsm: dict = field(default_factory=dict)         # (n_lp, n_hp) -> [nconf][npairs][T]
+    inversions: dict = field(default_factory=dict)  # key -> inversions per configuration
+
+    def rel_deviation(self, rows):
+        """Per pair: RMS over configurations and t of |estimate - exact|, over
+        the RMS of the exact value (the ensemble's own scale)."""
+        d = np.asarray(rows) - self.exact
+        return np.sqrt((np.abs(d) ** 2).mean(axis=(0, 2)) / (np.abs(self.exact) ** 2).mean(axis=(0, 2)))
+
+
+def run_loops(configs, dims, bc_t, kappa, n_noise=(4, 16, 64), schemes=tuple(SCHEMES), tsm=((64, 8),), seed=777,
+              hp=None, lp_tsm=None, exact_params=None, pairs=GAMMA_MOMENTA, tsm_dilution=0):
+    """configs: gauge fields U[4][V][3][3].  Noise as in the D(t) comparison:
+    complex Z2, configuration c seeded seed + 1000 c; stochastic estimates over
+    N vectors are the mean of the first N per-vector loops (Eq. loop
+    stochastic); TSM with seed + 1, noise indices from 0."""
+    T = dims[3]
+    hp = hp or SolverParams(tol=1e-8, solver=SOLVER_BICGSTAB)
+    lp_tsm = lp_tsm or SolverParams(tol=1e-2, truncated=True, solver=SOLVER_BICGSTAB)
+    exact_params = exact_params or SolverParams(tol=1e-12)
+    gam = sorted({g for g, _ in pairs})
+    moms = sorted({tuple(m) for _, m in pairs})
+    gi = {g: k for k, g in enumerate(gam)}
+    mi = {m: k for k, m in enumerate(moms)}
+    res = LoopStudyResult(T=T, pairs=tuple(pairs))
+    exact, stoch, tsm_rows = [], {}, {}
+    nmax = max(n_noise) if n_noise else 0
+    lat = Lattice(dims, bc_t)
+
+    def project(L):  # [ngam][T][Vs] -> [npairs][T]
+        P = lat.momentum_project(L, moms)
+        return np.array([P[gi[g], mi[tuple(m)]] for g, m in pairs])
+
+    try:
+        for ci, U in enumerate(configs):
+            lat.set_gauge(U)
+            lat.set_kappa(kappa)
+            cseed = seed + 1000 * ci
+            exact.append(project(lat.loops_exact(list(range(T)), gam, exact_params)))
+            for name in schemes:
+                dil, factor = SCHEMES[name]
+                per = [project(lat.loops_stochastic(NoiseParams(noise=NOISE_CZ2, seed=cseed, r0=r, n_lp=1, n_hp=0,
+                                                                dilution=dil, t_begin=0, t_end=T), gam, lp=hp))
+                       for r in range(nmax)]
+                for N in n_noise:
+                    stoch.setdefault((name, N), []).append(np.mean(per[:N], axis=0))
+                    res.inversions[(name, N)] = N * factor
+            for (n_lp, n_hp) in tsm:
+                q = NoiseParams(noise=NOISE_CZ2, seed=cseed + 1, r0=0, n_lp=n_lp, n_hp=n_hp, dilution=tsm_dilution,
+                                t_begin=0, t_end=T)
+                tsm_rows.setdefault((n_lp, n_hp), []).append(project(lat.loops_stochastic(q, gam, lp=lp_tsm, hp=hp)))
+                res.inversions[(n_lp, n_hp)] = (n_lp + n_hp, n_hp)  # (LP solves, HP solves)
+    finally:
+        lat.close()
+    res.exact = np.array(exact)
+    res.stochastic = {k: np.array(v) for k, v in stoch.items()}
+    res.tsm = {k: np.array(v) for k, v in tsm_rows.items()}
+    return res
+
+
+def table_loops(res: LoopStudyResult):
+    """Rows (method, inversions, {pair: relative deviation}) over the ensemble."""
+    names = [f"{PAIR_NAMES.get(g, g)} p={tuple(m)}" for g, m in res.pairs]
+    rows = []
+    for (name, N), v in sorted(res.stochastic.items()):
+        rows.append((f"{name} N={N}", res.inversions[(name, N)], dict(zip(names, res.rel_deviation(v)))))
+    for (n_lp, n_hp), v in sorted(res.tsm.items()):
+        rows.append((f"TSM LP={n_lp} HP={n_hp}", res.inversions[(n_lp, n_hp)],
+                     dict(zip(names, res.rel_deviation(v)))))
+    return rows
+
+
 def main(argv=None):
     """Run the comparison on a synthetic ensemble and print one JSON line."""
     import argparse
@@ -125,10 +215,20 @@ def main(argv=None):
     ap.add_argument("--noise", type=int, nargs="+", default=[4, 16, 64])
     ap.add_argument("--tsm", type=int, nargs="+", default=[64, 8, 256, 16], help="pairs n_lp n_hp")
     ap.add_argument("--t", type=int, default=3)
+    ap.add_argument("--loops", action="store_true",
+                    help="the per-insertion comparison of momentum-projected loops instead of D(t)")
     a = ap.parse_args(argv)
     dims = tuple(a.dims)
     configs = [S.random_links(dims, a.eps, 7000 + c) for c in range(a.configs)]
     t0 = time.perf_counter()
+    if a.loops:
+        res = run_loops(configs, dims, -1, a.kappa, n_noise=tuple(a.noise), tsm=tuple(zip(a.tsm[::2], a.tsm[1::2])))
+        dt = time.perf_counter() - t0
+        rows = [{"method": m, "inversions_per_config": inv, "rel_deviation": {k: round(float(x), 5) for k, x in d.items()}}
+                for m, inv, d in table_loops(res)]
+        print(json.dumps({"lattice": list(dims), "configs": a.configs, "eps": a.eps, "kappa": a.kappa,
+                          "seconds": round(dt, 1), "rows": rows}), flush=True)
+        return
     res = run(configs, dims, -1, a.kappa, n_noise=tuple(a.noise), tsm=tuple(zip(a.tsm[::2], a.tsm[1::2])))
     dt = time.perf_counter() - t0
     rows = [{"method": m, "inversions_per_config": inv, "D_mean": mu, "D_err": er} for m, inv, mu, er in table(res, a.t)]

@@ -49,3 +49,29 @@ def test_stochastic_error_shrinks_with_inversions(F):
     res = study.run(configs, dims, bc, kappa, n_noise=(2, 32), schemes=("even-odd",), tsm=(), seed=21)
     dev = {N: np.abs(res.stochastic[("even-odd", N)][:, 3] - res.exact[:, 3]).sum() for N in (2, 32)}
     assert dev[32] < 0.5 * dev[2], dev
+
+
+def test_loop_study_matches_oracle_2x2x2x4(F):
+    """The per-insertion comparison (g1..g4 at the lowest momenta, the scalar at
+    p = 0): every projected estimate per configuration, GPU against the
+    oracle's composition on the same noise (FP64 solves; the TSM's LP map as a
+    truncated FP64 solve at 1e-12 so both sides solve to the same accuracy)."""
+    from paper_1108_2473_amd import study
+    dims, bc, kappa = (2, 2, 2, 4), -1, 0.12
+    configs = [S.random_links(dims, 0.5, 5100 + c) for c in range(2)]
+    hp = F.SolverParams(tol=1e-12, inner_prec=F.PREC_F64, gauge_reals=18)
+    lp = F.SolverParams(tol=1e-12, truncated=True, inner_prec=F.PREC_F64, gauge_reals=18)
+    res = study.run_loops(configs, dims, bc, kappa, n_noise=(1, 3), tsm=((3, 2),), seed=13, hp=hp, lp_tsm=lp,
+                          exact_params=hp)
+    masks = {k: v[0] for k, v in study.SCHEMES.items()}
+    ref = O.loop_error_study(configs, dims, bc, kappa, (1, 3), masks, ((3, 2),), 13, 1e-13, 1e-13)
+    assert res.pairs == O.GAMMA_MOMENTA
+    scale = np.abs(ref["exact"]).max(axis=(0, 2))[None, :, None]
+    assert (np.abs(res.exact - ref["exact"]) / scale).max() <= 1e-9
+    for key, v in list(ref["stochastic"].items()):
+        assert (np.abs(res.stochastic[key] - v) / scale).max() <= 1e-9, key
+    for key, v in ref["tsm"].items():
+        assert (np.abs(res.tsm[key] - v) / scale).max() <= 1e-9, key
+    # the table's deviations are finite and shrink to 0 for no estimator here
+    for _, _, d in study.table_loops(res):
+        assert all(np.isfinite(x) and x > 0 for x in d.values())

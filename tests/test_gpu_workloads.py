@@ -66,8 +66,9 @@ def test_solver_16x16x16x32_stopping_rule(F):
 def test_uneven_tsm_batch(F):
     """8^4, 12^3x24 and 16^3x32 (eps 0.4/0.5/0.6, kappa 0.14) in one batch: 64
     complex-Z2 LP solves truncated at 1e-3 plus 4 FP64-corrected HP vectors each,
-    all Gamma.  Each lattice's estimate equals a separate single-lattice run bit
-    for bit, and the HP ensemble's estimate on 8^4 equals the oracle's."""
+    all Gamma.  Each of the three lattices' estimates equals a separate
+    single-lattice run bit for bit; the HP ensemble's estimate on 8^4 and one HP
+    vector's on 12^3x24 equal the oracle's."""
     names = ["tsm_8x8x8x8", "tsm_12x12x12x24", "tsm_16x16x16x32"]
     lats = [lattice(F, n) for n in names]
     lp = F.SolverParams(tol=1e-3, truncated=True)
@@ -75,8 +76,9 @@ def test_uneven_tsm_batch(F):
     qs = [F.NoiseParams(noise=F.NOISE_CZ2, seed=W["noise_seed"], r0=0, n_lp=64, n_hp=4, dilution=0,
                         t_begin=0, t_end=W["dims"][3]) for (_, _, W) in lats]
     multi = F.loops_stochastic_multi([l for (l, _, _) in lats], qs, GAMMAS, lp, hp)
-    single = lats[0][0].loops_stochastic(qs[0], GAMMAS, lp=lp, hp=hp)
-    assert np.array_equal(single, multi[0])
+    for (lat, _, _), q, m in zip(lats, qs, multi):
+        single = lat.loops_stochastic(q, GAMMAS, lp=lp, hp=hp)
+        assert np.array_equal(single, m)
     for m in multi:
         assert np.all(np.isfinite(m))
         assert np.abs(m[0].imag).max() < 1e-2 * np.abs(m[0].real).max() + 1.0
@@ -87,12 +89,53 @@ def test_uneven_tsm_batch(F):
     want = O.loops_stochastic(U8, W8["dims"], W8["bc_t"], W8["kappa"], O.NOISE_CZ2, W8["noise_seed"], 64, 4,
                               0, 0, 8, GAMMAS, tol=1e-13)
     assert np.abs(got - want).max() / np.abs(want[0]).max() <= 1e-10
+    lat12, U12, W12 = lats[1]
+    q = F.NoiseParams(noise=F.NOISE_CZ2, seed=W12["noise_seed"], r0=64, n_lp=1, dilution=0, t_begin=0,
+                      t_end=24)
+    got = lat12.loops_stochastic(q, GAMMAS, lp=hp)
+    want = O.loops_stochastic(U12, W12["dims"], W12["bc_t"], W12["kappa"], O.NOISE_CZ2, W12["noise_seed"], 64, 1,
+                              0, 0, 24, GAMMAS, tol=1e-13)
+    assert np.abs(got - want).max() / np.abs(want[0]).max() <= 1e-10
 
 
-def test_gradient_12x12x12x24_finite_differences(F):
+@pytest.mark.parametrize("prec", [1, 2], ids=["f32", "bf16"])
+def test_exact_loops_8x8x8x16_batches(F, prec):
+    """The exact timeslice workload (8^3x16, eps 0.5, kappa 0.14): FP32- or
+    bf16-link BiCGStab with FP64 reliable updates to 1e-12, the whole timeslice
+    t0 = 0 (6144 point sources) in batches of 96 right-hand sides, checked at
+    sampled sites of both parities against the oracle (e <= 1e-10); a site subset
+    solved in batches of 12, 24 and 48 gives the same values bit for bit (per-
+    system recurrences, reductions over fixed site blocks, host checks at fixed
+    iterations)."""
+    lat, U, W = lattice(F, "exact_8x8x8x16")
+    dims = W["dims"]
+    got = lat.loops_exact([0], GAMMAS, F.SolverParams(tol=1e-12, inner_prec=prec, batch=96))
+    sample = [0, 1, 137, 200, 511]  # lexicographic sites of t = 0, both parities
+    want = O.loops_exact_sites(U, dims, W["bc_t"], W["kappa"], sample, GAMMAS, tol=1e-14)
+    scale = np.abs(want[0]).max()
+    assert np.abs(got[:, 0, sample] - want).max() / scale <= 1e-10
+    assert np.abs(got[0:2, 0].imag).max() < 1e-10 * scale
+    assert np.abs(got[2:6, 0].real).max() < 1e-10 * scale
+    subset = [3, 4, 64, 65, 130, 131, 300, 301]
+    for batch in (12, 24, 48):
+        part = lat.loops_exact_sites(subset, GAMMAS, F.SolverParams(tol=1e-12, inner_prec=prec, batch=batch))
+        assert np.array_equal(part, got[:, 0, subset]), batch
+
+
+GRAD_PRECS = [("f64", dict(tol=1e-13, inner_prec=0, gauge_reals=18)),
+              ("f32", dict(tol=1e-13, inner_prec=1, gauge_reals=12)),
+              ("h16 cgnr", dict(tol=1e-13, inner_prec=3, gauge_reals=12, solver=1))]
+
+
+@pytest.mark.parametrize("name,kw", GRAD_PRECS, ids=[g[0] for g in GRAD_PRECS])
+def test_gradient_12x12x12x24_finite_differences(F, name, kw):
     """12^3x24, kappa 0.14, eps 0.5: gradients of sum_x Re L_Gamma(x) (Gamma = 1, g5)
-    over a site subset W of timeslice 0 with respect to kappa and the links, against
-    central finite differences (h = 1e-5) on 20 random Lie directions."""
+    over a site subset W (8 sites) of timeslice 0 with respect to kappa and the
+    links, against central finite differences (h = 1e-5) on 20 random Lie
+    directions, with FP64 iterations and with the mixed-precision FP32 and 16-bit
+    iterations (FP64 reliable updates), every solve to 1e-13: a loop error e
+    enters the central difference as ~e / h, so e ~ 1e-13 |L| keeps that noise
+    near 1e-8 |L|, below the 1e-6 tolerance."""
     lat, U, W = lattice(F, "grad_12x12x12x24")
     dims = W["dims"]
     Vs = dims[0] * dims[1] * dims[2]
@@ -100,7 +143,7 @@ def test_gradient_12x12x12x24_finite_differences(F):
     sites = rng.choice(Vs, 8, replace=False)
     w = np.zeros((2, 1, Vs), complex)
     w[:, 0, sites] = 1.0
-    prm = F.SolverParams(tol=1e-13, inner_prec=F.PREC_F64, gauge_reals=18)
+    prm = F.SolverParams(**kw)
     dU, dk = lat.loops_grad([0], [0, 15], w, prm)
     V = S.volume(dims)
 
