@@ -68,6 +68,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# vector passes (fields read or written once per site and right-hand side) of
+# one Krylov iteration, besides the links: CGNR with the carried normal
+# residual: q = Dhat p (hop 2 + hop with p own and q out 3), z -= alpha Dhat^+ q
+# (hop 2 + hop with q own, z own and z out 4), x += alpha p, p = z + beta p
+# (p, z, x in; x, p out: 5); BiCGStab: Dhat p with <r0, v> (2 + 4), s = r -
+# alpha v (3), Dhat s with <t, s>, |t|^2 (2 + 3), x and r update (5 in, 2 out),
+# p update (3 in, 1 out)
+ITER_PASSES = {"cgnr": 16, "bicgstab": 25}
+ITER_HOPS = 4  # hopping launches per iteration, each reading the links of every site once
+
+
+def iteration_roofline(solver, prec, Vh, system_iterations, launches_per_step, seconds_per_step):
+    """Algorithmic bytes of the Krylov iteration kernels of one step (vector
+    passes per system-iteration and site, links once per hopping launch) over
+    the whole step's time: the rate of the iteration as a whole, replacements,
+    host checks, noise and contraction included in the time only."""
+    vec = ITER_PASSES[solver] * SITE_BYTES[prec] * Vh * system_iterations
+    lnk = 8 * LINK_BYTES[prec] * Vh * launches_per_step
+    gbs = (vec + lnk) / seconds_per_step / 1e9
+    return {"bytes_per_site_and_system_iteration": ITER_PASSES[solver] * SITE_BYTES[prec],
+            "system_iterations_per_step": system_iterations, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def cpu_model():
     """Model name of the host CPU (/proc/cpuinfo), or the platform string."""
     try:
@@ -411,6 +435,8 @@ def main():
             "launches": prof["launches"],
             "algorithmic_bytes_per_launch": round(bytes_per_launch),
         },
+        "iteration_roofline": iteration_roofline(args.solver, args.prec, Vh, float(iters.sum()) / args.steps,
+                                                 ITER_HOPS * float(iters.max()), T / args.steps),
         "cpu_baseline": cpu,
         "timed_solves": solves_summary,
         "fp64_single_rhs_gpu_solves_per_s": round(fp64_rate, 3),

@@ -355,6 +355,21 @@ fl_status fl_disconnected_corr(fl_ctx *ctx, const double *Lp1, const double *Lp2
 fl_status fl_smear(fl_ctx *ctx, double *psi, int nrhs, double alpha, int n, double norm,
                    fl_where where);
 
+/* APE smearing of the spatial links that enter the Gaussian smearing kernel
+ * H (Sec. III applies it; the paper states neither its form nor its
+ * parameters): n steps of, for i = 1..3,
+ *   U'_i(x) = P[ U_i(x) + alpha sum_{j=1..3, j != i} ( U_j(x) U_i(x+j) U_j(x+i)^+
+ *                                               + U_j(x-j)^+ U_i(x-j) U_j(x-j+i) ) ],
+ * P(V) = W exp(-i arg(det W) / 3) with W the unitary factor of the polar
+ * decomposition V = W (V^+ V)^{1/2} and arg in (-pi, pi] (an SU(3) matrix;
+ * V must be nonsingular).  The time links are unchanged.  FP64.  The
+ * smeared links stay in the context and are used by fl_smear and
+ * fl_pion_corr (the Dirac operator keeps the unsmeared links) until the
+ * next fl_set_gauge or a call with n = 0, which returns to the unsmeared
+ * links.  Uout: NULL, or [4][V][3][3][2] in `where` memory receiving the
+ * smeared field.  alpha >= 0 finite, n >= 0. */
+fl_status fl_ape_smear(fl_ctx *ctx, double alpha, int n, double *Uout, fl_where where);
+
 /* Connected pseudoscalar two-point function (Sec. III, Eq. all_corr with
  * Gamma_A = Gamma_B = g5) from a point source at lexicographic site y0,
  * smeared at the source and/or the sink with F of fl_smear:

@@ -321,6 +321,44 @@ def smear(U, psi, dims, alpha, n, norm=1.0):
     return psi
 
 
+def su3_project(V):
+    """The SU(3) matrix assigned to a nonsingular 3x3 complex V (last two axes):
+    the unitary factor W of the polar decomposition V = W P (W = A B^+ from the
+    singular value decomposition V = A S B^+), divided by a cube root of its
+    determinant, det(W)^(1/3) = exp(i arg(det W) / 3) with arg in (-pi, pi]."""
+    A, _, Bh = np.linalg.svd(V)
+    W = A @ Bh
+    ph = np.angle(np.linalg.det(W))
+    return W * np.exp(-1j * ph / 3)[..., None, None]
+
+
+def ape_smear(U, dims, alpha, n):
+    """APE smearing of the spatial links (Sec. III: the links entering the
+    smearing kernel H are APE smeared; the paper does not give its form or
+    parameters), n steps of
+        U'_i(x) = P_SU3[ U_i(x) + alpha sum_{j=1..3, j != i} ( U_j(x) U_i(x+j) U_j(x+i)^+
+                                                          + U_j(x-j)^+ U_i(x-j) U_j(x-j+i) ) ]
+    with P_SU3 of su3_project; the time links are returned unchanged."""
+    U = np.array(U, dtype=np.complex128, copy=True)
+    for _ in range(n):
+        new = U.copy()
+        for i in range(3):
+            fi = _shift_index(dims, i, +1)
+            acc = U[i].copy()
+            for j in range(3):
+                if j == i:
+                    continue
+                fj = _shift_index(dims, j, +1)
+                bj = _shift_index(dims, j, -1)
+                dag = lambda M: M.conj().transpose(0, 2, 1)
+                up = U[j] @ U[i][fj] @ dag(U[j][fi])
+                dn = dag(U[j][bj]) @ U[i][bj] @ U[j][fi[bj]]
+                acc = acc + alpha * (up + dn)
+            new[i] = su3_project(acc)
+        U = new
+    return U
+
+
 def point_sources(dims, y0):
     """The 12 spin-colour point sources at lexicographic site y0: [12][V][4][3]."""
     V = int(np.prod(dims))
@@ -331,20 +369,23 @@ def point_sources(dims, y0):
 
 
 def pion_correlator(U, dims, bc_t, kappa, y0, mom, alpha=0.0, n=0, norm=1.0, smear_source=False,
-                    smear_sink=False, tol=1e-13):
+                    smear_sink=False, tol=1e-13, U_smear=None):
     """Connected pseudoscalar two-point function of Eq. (all_corr) with
     Gamma_A = Gamma_B = g5 and a point source at y0 (optionally smeared):
     by g5-hermiticity Tr[g5 G(x;y0) g5 G(y0;x)] = sum |G(x;y0)|^2, so
     C[k][t] = sum_x exp(+i p_k.(x - y0)) sum_{sources, components} |phi(x, t0 + t)|^2
-    with phi = F_sink D^-1 F_source e_{y0} (F = identity when not smeared)."""
+    with phi = F_sink D^-1 F_source e_{y0} (F = identity when not smeared).
+    The smearing kernel uses the links U_smear (e.g. APE smeared) when given,
+    the Dirac operator always U."""
+    Us = U if U_smear is None else U_smear
     b = point_sources(dims, y0)
     if smear_source:
-        b = smear(U, b, dims, alpha, n, norm)
+        b = smear(Us, b, dims, alpha, n, norm)
     x, it, res, fails = solve(U, b, dims, bc_t, kappa, tol=tol)
     if fails:
         raise RuntimeError("oracle solve did not converge")
     if smear_sink:
-        x = smear(U, x, dims, alpha, n, norm)
+        x = smear(Us, x, dims, alpha, n, norm)
     Vs = dims[0] * dims[1] * dims[2]
     T = dims[3]
     rho = np.sum(np.abs(x) ** 2, axis=(0, 2, 3)).reshape(T, Vs)  # [t][xs]

@@ -149,6 +149,7 @@ def lib():
     L.fl_autotune.argtypes = [vp, i, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i), dp]
     L.fl_momentum_project.argtypes = [vp, vp, i, i, ctypes.POINTER(i), i, vp, i]
     L.fl_smear.argtypes = [vp, vp, i, d, i, d, i]
+    L.fl_ape_smear.argtypes = [vp, d, i, vp, i]
     L.fl_pion_corr.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(_SolverParams), d, i, d, i, i,
                                ctypes.POINTER(i), i, vp, i]
     L.fl_disconnected_corr.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(i), i, vp, i]
@@ -158,7 +159,7 @@ def lib():
                  "fl_apply_schur", "fl_solve", "fl_loops_exact", "fl_loops_exact_sites", "fl_loops_stochastic",
                  "fl_loops_stochastic_multi", "fl_loops_grad", "fl_profile_enable", "fl_profile_read",
                  "fl_bench_dslash", "fl_set_tile", "fl_autotune", "fl_momentum_project", "fl_disconnected_corr", "fl_smear",
-                 "fl_pion_corr", "fl_last_stats", "fl_apply_D_noalloc"):
+                 "fl_pion_corr", "fl_last_stats", "fl_apply_D_noalloc", "fl_ape_smear"):
         getattr(L, name).restype = i
     _lib = L
     return L
@@ -389,6 +390,16 @@ class Lattice:
         self._check(lib().fl_momentum_project(self._h, ctypes.c_void_p(a.ptr), ng, nt,
                                               m.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), m.shape[0],
                                               ctypes.c_void_p(optr), a.where))
+        return out
+
+    def ape_smear(self, alpha=0.5, n=20, want_links=True):
+        """APE-smear the spatial links used by the Gaussian smearing kernel
+        (fl_ape_smear; kept for smear and pion_corr, the Dirac operator keeps
+        the unsmeared links; n = 0 returns to the unsmeared links).  Returns
+        the smeared field U'[4][V][3][3] (numpy) when want_links."""
+        out = np.empty((4, self.V, 3, 3), dtype=np.complex128) if want_links else None
+        self._check(lib().fl_ape_smear(self._h, float(alpha), int(n),
+                                       ctypes.c_void_p(out.ctypes.data) if want_links else None, FL_HOST))
         return out
 
     def smear(self, psi, alpha=4.0, n=50, norm=1.0):

@@ -524,6 +524,7 @@ fl_status fl_destroy(fl_ctx *c)
     for (int k = 0; k < LINK_NFMT; ++k)
         if (c->gauge[k]) hipFree(c->gauge[k]);
     if (c->gauge_canon) hipFree(c->gauge_canon);
+    if (c->smear_gauge) hipFree(c->smear_gauge);
     for (auto &p : c->prof) prof_reset(p);
     delete c;
     return FL_OK;
@@ -580,6 +581,7 @@ fl_status fl_set_gauge(fl_ctx *c, const double *U, fl_where where)
     if (!std::isfinite(dev)) return set_err(c, FL_ERR_ARG, "gauge field holds non-finite values");
     c->su3 = dev <= 1e-10;
     for (int k = 0; k < LINK_NFMT; ++k) c->gauge_ok[k] = false;
+    c->smear_ok = false;  // APE-smeared links belong to the previous field
     c->have_gauge = true;
     if (!links(c, LINK_F64_R18)) return set_err(c, FL_ERR_NOMEM, "device allocation failed (links)");
     return hip_check(c, hipStreamSynchronize(c->stream), "pack links");

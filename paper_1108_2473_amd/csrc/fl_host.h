@@ -276,6 +276,8 @@ struct fl_ctx {
     int tune_lds[LINK_NFMT] = {-1, -1, -1, -1, -1};  // LDS staging mode; -1: built-in choice
     size_t max_lds = 65536;              // LDS bytes a workgroup may use on this device
     std::vector<fl_solver_stats> last_stats;  // per-solve statistics of the last solving call
+    void *smear_gauge = nullptr;  // APE-smeared FP64 links (LINK_F64_R18 layout) for Gaussian smearing
+    bool smear_ok = false;        // smear_gauge holds the smearing of the current links
 };
 
 // LDS staging mode and window length for a hopping launch over batch B
@@ -311,7 +313,7 @@ enum {
     WS_T, WS_XL, WS_TMP, WS_PART, WS_STATE, WS_ACTIVE, WS_MASK, WS_SITES, WS_GAM, WS_ACC,
     WS_ACC2, WS_COMP, WS_M, WS_CE, WS_CO, WS_DU, WS_HE, WS_HO, WS_XE2, WS_XO2, WS_MISC,
     WS_CORR_A, WS_CORR_B, WS_CORR_OUT, WS_CORR_IDX, WS_SM_E0, WS_SM_O0, WS_SM_E1, WS_SM_O1, WS_PI_SRC,
-    WS_PI_SOL, WS_PI_RHO,
+    WS_PI_SOL, WS_PI_RHO, WS_APE0, WS_APE1,
     WS_NSLOTS
 };
 

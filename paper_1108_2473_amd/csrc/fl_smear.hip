@@ -116,13 +116,186 @@ __global__ void k_canon_point(double *src, long long V, long long y0)
 
 unsigned blocks(long long n) { return (unsigned)((n + BLK - 1) / BLK); }
 
+// ---------------------------------------------------------------------------
+// APE smearing of the spatial links (the links of H; Sec. III)
+// ---------------------------------------------------------------------------
+typedef cx<double> M3[3][3];
+
+__device__ __forceinline__ void m3_load(const double *U, long long V, int mu, long long s, M3 m)
+{
+    const double *p = U + ((size_t)mu * V + s) * 18;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m[e / 3][e % 3] = cx<double>{p[2 * e], p[2 * e + 1]};
+}
+
+// c = a b (ADJB: a b^+; ADJA: a^+ b)
+template <bool ADJA, bool ADJB>
+__device__ __forceinline__ void m3_mul(const M3 a, const M3 b, M3 c)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<double> acc{0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const cx<double> x = ADJA ? cj(a[k][i]) : a[i][k];
+                const cx<double> y = ADJB ? cj(b[j][k]) : b[k][j];
+                acc = cmad(acc, x, y);
+            }
+            c[i][j] = acc;
+        }
+}
+
+__device__ __forceinline__ cx<double> m3_det(const M3 m)
+{
+    return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+           m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+}
+
+__device__ __forceinline__ double m3_norm2(const M3 m)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) s += m[e / 3][e % 3].re * m[e / 3][e % 3].re + m[e / 3][e % 3].im * m[e / 3][e % 3].im;
+    return s;
+}
+
+// the SU(3) matrix assigned to a nonsingular V: the unitary factor W of the
+// polar decomposition V = W P, by the scaled Newton iteration
+// W <- (g W + (g W)^{-+}) / 2 (Higham 1986; quadratic convergence, g the
+// Frobenius-norm scaling), divided by exp(i arg(det W) / 3), arg in (-pi, pi]
+__device__ void su3_project(M3 W)
+{
+    for (int it = 0; it < 40; ++it) {
+        // inverse by the adjugate: inv[i][j] = cof[j][i] / det
+        const cx<double> d = m3_det(W);
+        const double dd = d.re * d.re + d.im * d.im;
+        const cx<double> di{d.re / dd, -d.im / dd};
+        M3 inv;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+                inv[i][j] = (W[r0][c0] * W[r1][c1] - W[r0][c1] * W[r1][c0]) * di;
+            }
+        const double g = it < 6 ? sqrt(sqrt(m3_norm2(inv) / m3_norm2(W))) : 1.0;
+        double delta = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                // (inv^+)[i][j] = conj(inv[j][i])
+                const cx<double> n{0.5 * (g * W[i][j].re + inv[j][i].re / g), 0.5 * (g * W[i][j].im - inv[j][i].im / g)};
+                delta += (n.re - W[i][j].re) * (n.re - W[i][j].re) + (n.im - W[i][j].im) * (n.im - W[i][j].im);
+                W[i][j] = n;
+            }
+        if (g == 1.0 && delta < 1e-30) break;
+    }
+    const cx<double> d = m3_det(W);
+    const double ph = -atan2(d.im, d.re) / 3.0;
+    const cx<double> f{cos(ph), sin(ph)};
+#pragma unroll
+    for (int e = 0; e < 9; ++e) W[e / 3][e % 3] = W[e / 3][e % 3] * f;
+}
+
+struct ApeArgs {
+    const double *in;  // canonical links [4][V][3][3][2]
+    double *out;
+    long long V;
+    int L[4];
+    double alpha;
+};
+
+// one APE step for the spatial link (i, s); the time links are copied
+__global__ __launch_bounds__(BLK) void k_ape_step(ApeArgs a)
+{
+    const long long id = blockIdx.x * (long long)BLK + threadIdx.x;
+    if (id >= 4 * a.V) return;
+    const int i = (int)(id / a.V);
+    const long long s = id - (long long)i * a.V;
+    double *o = a.out + ((size_t)i * a.V + s) * 18;
+    const double *p = a.in + ((size_t)i * a.V + s) * 18;
+    if (i == 3) {
+        double v[18];
+#pragma unroll
+        for (int k = 0; k < 18; ++k) v[k] = p[k];
+        double *const q[18] = {o, o + 1, o + 2, o + 3, o + 4, o + 5, o + 6, o + 7, o + 8,
+                               o + 9, o + 10, o + 11, o + 12, o + 13, o + 14, o + 15, o + 16, o + 17};
+        ptr_store_group<18, double>(q, v);
+        return;
+    }
+    int x[4];
+    long long r = s;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        x[m] = (int)(r % a.L[m]);
+        r /= a.L[m];
+    }
+    auto idx = [&](const int y[4]) -> long long {
+        return y[0] + (long long)a.L[0] * (y[1] + (long long)a.L[1] * (y[2] + (long long)a.L[2] * y[3]));
+    };
+    M3 acc, A, B, C, T1, T2;
+    m3_load(a.in, a.V, i, s, acc);
+    int xi[4] = {x[0], x[1], x[2], x[3]};
+    xi[i] = (x[i] + 1) % a.L[i];
+    for (int j = 0; j < 3; ++j) {
+        if (j == i) continue;
+        int xj[4] = {x[0], x[1], x[2], x[3]}, xmj[4] = {x[0], x[1], x[2], x[3]};
+        xj[j] = (x[j] + 1) % a.L[j];
+        xmj[j] = (x[j] + a.L[j] - 1) % a.L[j];
+        int xmji[4] = {xmj[0], xmj[1], xmj[2], xmj[3]};
+        xmji[i] = (xmj[i] + 1) % a.L[i];
+        // U_j(x) U_i(x + j) U_j(x + i)^+
+        m3_load(a.in, a.V, j, s, A);
+        m3_load(a.in, a.V, i, idx(xj), B);
+        m3_load(a.in, a.V, j, idx(xi), C);
+        m3_mul<false, false>(A, B, T1);
+        m3_mul<false, true>(T1, C, T2);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            acc[e / 3][e % 3].re = fma(a.alpha, T2[e / 3][e % 3].re, acc[e / 3][e % 3].re);
+            acc[e / 3][e % 3].im = fma(a.alpha, T2[e / 3][e % 3].im, acc[e / 3][e % 3].im);
+        }
+        // U_j(x - j)^+ U_i(x - j) U_j(x - j + i)
+        m3_load(a.in, a.V, j, idx(xmj), A);
+        m3_load(a.in, a.V, i, idx(xmj), B);
+        m3_load(a.in, a.V, j, idx(xmji), C);
+        m3_mul<true, false>(A, B, T1);
+        m3_mul<false, false>(T1, C, T2);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            acc[e / 3][e % 3].re = fma(a.alpha, T2[e / 3][e % 3].re, acc[e / 3][e % 3].re);
+            acc[e / 3][e % 3].im = fma(a.alpha, T2[e / 3][e % 3].im, acc[e / 3][e % 3].im);
+        }
+    }
+    su3_project(acc);
+    double v[18];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        v[2 * e] = acc[e / 3][e % 3].re;
+        v[2 * e + 1] = acc[e / 3][e % 3].im;
+    }
+    double *const q[18] = {o, o + 1, o + 2, o + 3, o + 4, o + 5, o + 6, o + 7, o + 8,
+                           o + 9, o + 10, o + 11, o + 12, o + 13, o + 14, o + 15, o + 16, o + 17};
+    ptr_store_group<18, double>(q, v);
+}
+
+// links of the smearing kernel H: APE-smeared when fl_ape_smear made them
+const double2 *smear_links(fl_ctx *c)
+{
+    if (c->smear_ok && c->smear_gauge) return (const double2 *)c->smear_gauge;
+    return (const double2 *)links(c, LINK_F64_R18);
+}
+
 // F^n on canonical fields in place (device), through checkerboard copies
 fl_status smear_canon(fl_ctx *c, double *canon, int nrhs, double alpha, int n, double norm)
 {
     const size_t fb = (size_t)nrhs * c->Vh * 192;
     double2 *e0 = (double2 *)ws_get(c, WS_SM_E0, fb), *o0 = (double2 *)ws_get(c, WS_SM_O0, fb);
     double2 *e1 = (double2 *)ws_get(c, WS_SM_E1, fb), *o1 = (double2 *)ws_get(c, WS_SM_O1, fb);
-    const double2 *gauge = (const double2 *)links(c, LINK_F64_R18);
+    const double2 *gauge = smear_links(c);
     if (!e0 || !o0 || !e1 || !o1 || !gauge) return set_err(c, FL_ERR_NOMEM, "device allocation failed (smearing)");
     LatGeom g = lat_geom(c, nrhs);
     launch_canon_to_eo(canon, e0, o0, g, nrhs, c->stream);
@@ -231,4 +404,45 @@ fl_status fl_pion_corr(fl_ctx *c, long long y0, const fl_solver_params *p, doubl
         return e;
     if ((e = hip_check(c, hipStreamSynchronize(c->stream), "pion correlator"))) return e;
     return se == FL_OK ? FL_OK : set_err(c, se, "some point-source solves did not reach tol (fl_last_stats)");
+}
+
+fl_status fl_ape_smear(fl_ctx *c, double alpha, int n, double *Uout, fl_where where)
+{
+    if (!c) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
+    if (!(alpha >= 0) || !std::isfinite(alpha) || n < 0)
+        return set_err(c, FL_ERR_ARG, "APE smearing needs a finite alpha >= 0 and n >= 0");
+    if (where != FL_HOST && where != FL_DEVICE) return set_err(c, FL_ERR_ARG, "bad `where`");
+    if (!c->have_gauge) return set_err(c, FL_ERR_STATE, "gauge field not set (fl_set_gauge)");
+    hipSetDevice(c->device);
+    const size_t ub = (size_t)4 * c->V * 18 * sizeof(double);
+    fl_status e;
+    double *cur = c->gauge_canon;
+    if (n > 0) {
+        double *b0 = (double *)ws_get(c, WS_APE0, ub), *b1 = (double *)ws_get(c, WS_APE1, ub);
+        if (!b0 || !b1) return set_err(c, FL_ERR_NOMEM, "device allocation failed (APE smearing)");
+        if (!c->smear_gauge && hipMalloc(&c->smear_gauge, link_bytes(LINK_F64_R18) * 4 * (size_t)c->V) != hipSuccess) {
+            c->smear_gauge = nullptr;
+            (void)hipGetLastError();
+            return set_err(c, FL_ERR_NOMEM, "device allocation failed (APE-smeared links)");
+        }
+        ApeArgs a;
+        a.V = c->V;
+        for (int m = 0; m < 4; ++m) a.L[m] = c->L[m];
+        a.alpha = alpha;
+        for (int k = 0; k < n; ++k) {
+            a.in = cur;
+            a.out = (k % 2 == 0) ? b0 : b1;
+            hipLaunchKernelGGL(k_ape_step, dim3(blocks(4 * c->V)), dim3(BLK), 0, c->stream, a);
+            cur = a.out;
+        }
+        launch_pack_links(cur, c->smear_gauge, LINK_F64_R18, lat_geom(c, 0), c->stream);
+        c->smear_ok = true;
+    } else {
+        c->smear_ok = false;
+    }
+    if (Uout &&
+        (e = hip_check(c, hipMemcpyAsync(Uout, cur, ub, where == FL_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                         c->stream), "copy APE-smeared links")))
+        return e;
+    return hip_check(c, hipStreamSynchronize(c->stream), "APE smearing");
 }

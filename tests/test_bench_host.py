@@ -43,3 +43,12 @@ def test_committed_profiles_carry_machine_readable_fields():
         txt = open(bench.traffic_profile(prec)).read()
         assert "kernel_source_sha256:" in txt and "traffic_bytes_per_launch:" in txt
         assert "rocprofv3 --kernel-trace --stats" in txt
+
+
+def test_iteration_roofline_counts_passes_and_links():
+    """16-bit CGNR: 16 vector passes of 52 bytes per site and system-iteration
+    plus 8 links of 24 bytes per site and hopping launch, over the step time."""
+    r = bench.iteration_roofline("cgnr", "h16", 65536, 384 * 400, 4 * 400, 2.5)
+    want = (16 * 52 * 65536 * 384 * 400 + 8 * 24 * 65536 * 4 * 400) / 2.5 / 1e9
+    assert abs(r["achieved"] - want) <= 0.05 and r["bytes_per_site_and_system_iteration"] == 832
+    assert abs(r["frac"] - want / 8000.0) <= 1e-4

@@ -77,3 +77,48 @@ def test_pion_correlator_8x8x8x16_paper_smearing(F):
     want = O.pion_correlator(U, dims, W["bc_t"], W["kappa"], 0, mom, 4.0, 50, 25.0, True, True, tol=1e-13)
     assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
     lat.close()
+
+
+@pytest.mark.parametrize("dims,eps,alpha,n", [((4, 4, 4, 4), 0.6, 0.5, 3), ((6, 4, 2, 4), 0.4, 0.3, 5),
+                                              ((8, 8, 8, 16), 0.5, 0.5, 20)])
+def test_ape_smearing_matches_oracle(F, dims, eps, alpha, n):
+    """APE-smeared links (Newton polar iteration on the GPU, SVD in the oracle)
+    against the oracle's to 1e-12, special unitary; n = 0 returns the
+    unsmeared field."""
+    U = S.random_links(dims, eps, 36)
+    lat = F.Lattice(dims, -1)
+    lat.set_gauge(U)
+    got = lat.ape_smear(alpha, n)
+    want = O.ape_smear(U, dims, alpha, n)
+    assert np.abs(got - want).max() <= 1e-12
+    assert np.abs(np.linalg.det(got) - 1).max() <= 1e-12
+    assert np.array_equal(lat.ape_smear(alpha, 0), U)
+    lat.close()
+
+
+def test_pion_correlator_with_ape_links(F):
+    """The paper's setup: Gaussian smearing (alpha 4, n 20, norm 1 + 6 alpha)
+    with APE-smeared links in H (alpha_APE 0.5, 10 steps), the Dirac operator
+    on the unsmeared links; against the oracle; a new gauge field discards
+    the smeared links."""
+    dims = (4, 4, 4, 8)
+    kappa = 0.12
+    U = S.random_links(dims, 0.5, 37)
+    lat = F.Lattice(dims, -1)
+    lat.set_gauge(U)
+    lat.set_kappa(kappa)
+    Ua = lat.ape_smear(0.5, 10)
+    mom = [(0, 0, 0), (1, 0, 0)]
+    y0 = 77
+    prm = F.SolverParams(tol=1e-12, inner_prec=F.PREC_F64, gauge_reals=18)
+    got = lat.pion_corr(y0, prm, 4.0, 20, 25.0, True, True, mom)
+    want = O.pion_correlator(U, dims, -1, kappa, y0, mom, 4.0, 20, 25.0, True, True, tol=1e-14,
+                             U_smear=O.ape_smear(U, dims, 0.5, 10))
+    assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+    plain = O.pion_correlator(U, dims, -1, kappa, y0, mom, 4.0, 20, 25.0, True, True, tol=1e-14)
+    assert np.abs(plain - want).max() > 1e-3 * np.abs(want).max()  # the links of H matter
+    psi = S.random_spinors(dims, 2, 38)
+    assert np.abs(lat.smear(psi, 4.0, 3, 25.0) - O.smear(Ua, psi, dims, 4.0, 3, 25.0)).max() <= 1e-12
+    lat.set_gauge(U)
+    assert np.abs(lat.smear(psi, 4.0, 3, 25.0) - O.smear(U, psi, dims, 4.0, 3, 25.0)).max() <= 1e-12
+    lat.close()
