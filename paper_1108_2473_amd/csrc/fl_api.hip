@@ -302,6 +302,25 @@ fl_status hip_check(fl_ctx *c, hipError_t e, const char *what)
                    std::string(what) + ": " + hipGetErrorString(e));
 }
 
+void *pinned_get(fl_ctx *c, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (c->pinned_bytes >= bytes) return c->pinned;
+    if (c->pinned) {
+        hipStreamSynchronize(c->stream);
+        hipHostFree(c->pinned);
+        c->pinned = nullptr;
+        c->pinned_bytes = 0;
+    }
+    if (hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+        c->pinned = nullptr;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    c->pinned_bytes = bytes;
+    return c->pinned;
+}
+
 void *ws_get(fl_ctx *c, int slot, size_t bytes)
 {
     if ((int)c->pool.size() < WS_NSLOTS) c->pool.resize(WS_NSLOTS);
@@ -521,6 +540,7 @@ fl_status fl_destroy(fl_ctx *c)
     hipStreamSynchronize(c->stream);
     for (auto &b : c->pool)
         if (b.p) hipFree(b.p);
+    if (c->pinned) hipHostFree(c->pinned);
     for (int k = 0; k < LINK_NFMT; ++k)
         if (c->gauge[k]) hipFree(c->gauge[k]);
     if (c->gauge_canon) hipFree(c->gauge_canon);

@@ -278,7 +278,13 @@ struct fl_ctx {
     std::vector<fl_solver_stats> last_stats;  // per-solve statistics of the last solving call
     void *smear_gauge = nullptr;  // APE-smeared FP64 links (LINK_F64_R18 layout) for Gaussian smearing
     bool smear_ok = false;        // smear_gauge holds the smearing of the current links
+    void *pinned = nullptr;       // page-locked host staging of the solver's per-system state and masks
+    size_t pinned_bytes = 0;
 };
+
+// page-locked host memory of at least `bytes` owned by the context (grown,
+// contents not kept; the stream is synchronised before an old block is freed)
+void *pinned_get(fl_ctx *c, size_t bytes);
 
 // LDS staging mode and window length for a hopping launch over batch B
 void dslash_config(const fl_ctx *c, LinkFormat fmt, DslashArgs &a);

@@ -28,6 +28,24 @@ struct MF {  // one field per lattice
     void *p[FL_MAXLAT] = {nullptr, nullptr, nullptr, nullptr};
 };
 
+// a host array in the context's page-locked staging block: transfers of the
+// per-system state and masks between host checks are then DMA copies
+// without a pageable bounce (a block is rewritten only after the stream has
+// been synchronised past its last transfer, which every host check does)
+template <typename T>
+struct PinArr {
+    T *p = nullptr;
+    size_t n = 0;
+    T &operator[](size_t i) { return p[i]; }
+    const T &operator[](size_t i) const { return p[i]; }
+    T *data() { return p; }
+    size_t size() const { return n; }
+    void assign(size_t m, const T &v)
+    {
+        for (size_t i = 0; i < m && i < n; ++i) p[i] = v;
+    }
+};
+
 struct Solver {
     SolveBatch &sb;
     const fl_solver_params &prm;
@@ -46,8 +64,8 @@ struct Solver {
     SysState *dst = nullptr;
     int stamp = 0;  // CGNR iteration stamp
     int *active = nullptr, *mask = nullptr;
-    std::vector<SysState> hst;
-    std::vector<int> hact, hmask;
+    PinArr<SysState> hst;
+    PinArr<int> hact, hmask, hm2;  // hm2: the masks of restarts and CGNR replacements
     std::vector<long long> active_count;  // per lattice, at the last check
 
     Solver(SolveBatch &b, const fl_solver_params &p) : sb(b), prm(p) {}
@@ -278,6 +296,19 @@ fl_status Solver::prepare()
     active = (int *)ws_get(c0, WS_ACTIVE, sizeof(int) * nsys);
     mask = (int *)ws_get(c0, WS_MASK, sizeof(int) * nsys);
     if (!partial || !dst || !active || !mask) return set_err(c0, FL_ERR_NOMEM, "device allocation failed");
+    {
+        // [SysState x nsys][hact][hmask][hm2], SysState is 8-byte aligned
+        const size_t ns = (size_t)nsys;
+        char *h = (char *)pinned_get(c0, sizeof(SysState) * ns + 3 * sizeof(int) * ns + 64);
+        if (!h) return set_err(c0, FL_ERR_NOMEM, "page-locked host allocation failed");
+        hst.p = (SysState *)h;
+        hst.n = ns;
+        int *ip = (int *)(h + sizeof(SysState) * ns);
+        hact.p = ip;
+        hmask.p = ip + ns;
+        hm2.p = ip + 2 * ns;
+        hact.n = hmask.n = hm2.n = ns;
+    }
     return hip_check(c0, hipMemsetAsync(partial, 0, sizeof(double) * 6 * (size_t)nsys * B.nsb_max, st), "memset");
 }
 
@@ -421,7 +452,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
         // check the state every chunk of iterations
         bool any_active = false;
         for (int k = 0; k < nsys; ++k) any_active |= (hact[k] != 0);
-        act_start = hact;
+        act_start.assign(hact.data(), hact.data() + nsys);
         if (any_active)
             for (int it = 0; it < chunk; ++it) {
                 if (solver == FL_SOLVER_CGNR)
@@ -490,9 +521,8 @@ fl_status Solver::run(std::vector<SysResult> &res)
         }
         if (any_restart) {
             // breakdown: fresh recurrence from the current FP64 iterate
-            std::vector<int> m(nsys, 0);
-            for (int k = 0; k < nsys; ++k) m[k] = restart[k];
-            if ((e = hip_check(c0, hipMemcpyAsync(mask, m.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
+            for (int k = 0; k < nsys; ++k) hm2[k] = restart[k];
+            if ((e = hip_check(c0, hipMemcpyAsync(mask, hm2.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
                                "upload mask")))
                 return e;
             replace_residual(mask, 1);
@@ -549,9 +579,8 @@ fl_status Solver::run(std::vector<SysResult> &res)
             if (solver == FL_SOLVER_CGNR) {
                 // CGNR continues from the replaced residual with the same
                 // search direction: z = Dhat^+ r and |z|^2 are recomputed
-                std::vector<int> m(nsys, 0);
-                for (int k = 0; k < nsys; ++k) m[k] = hmask[k] && hact[k];
-                if ((e = hip_check(c0, hipMemcpyAsync(mask, m.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
+                for (int k = 0; k < nsys; ++k) hm2[k] = hmask[k] && hact[k];
+                if ((e = hip_check(c0, hipMemcpyAsync(mask, hm2.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st),
                                    "upload mask")))
                     return e;
                 cg_rez(mask);
