@@ -169,8 +169,15 @@ fl_status norms64(fl_ctx *c, int nrhs, const void *fe, const void *fo, std::vect
     a.slot0 = 3;
     a.f[0][0] = (void *)fo;
     launch_blas(VEC_F64, a, c->stream);
-    std::vector<double> h(np);
-    if ((e = hip_check(c, hipMemcpyAsync(h.data(), part, np * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+    // the two slots written (2 and 5), through the page-locked block
+    const size_t per = (size_t)nrhs * B.nsb_max;
+    double *h = (double *)pinned_get(c, 2 * per * sizeof(double));
+    if (!h) return set_err(c, FL_ERR_NOMEM, "page-locked host allocation failed");
+    if ((e = hip_check(c, hipMemcpyAsync(h, part + 2 * per, per * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                       "download norms")))
+        return e;
+    if ((e = hip_check(c, hipMemcpyAsync(h + per, part + 5 * per, per * sizeof(double), hipMemcpyDeviceToHost,
+                                         c->stream),
                        "download norms")))
         return e;
     if ((e = hip_check(c, hipStreamSynchronize(c->stream), "sync"))) return e;
@@ -178,7 +185,7 @@ fl_status norms64(fl_ctx *c, int nrhs, const void *fe, const void *fo, std::vect
     const int nsb = B.lat[0].nsb, nb = B.nsb_max;
     for (int k = 0; k < nrhs; ++k) {
         double s = 0;
-        for (int sb = 0; sb < nsb; ++sb) s += h[(2 * (size_t)nrhs + k) * nb + sb] + h[(5 * (size_t)nrhs + k) * nb + sb];
+        for (int sb = 0; sb < nsb; ++sb) s += h[(size_t)k * nb + sb] + h[per + (size_t)k * nb + sb];
         out[k] = s;
     }
     return FL_OK;
@@ -1015,13 +1022,16 @@ fl_status fl_loops_stochastic_multi(fl_ctx **ctxs, int nctx, const fl_noise_para
                 sb.bh[l] = (const double2 *)bh;
                 sb.xh[l] = (double2 *)xe;
                 if (n == 0) continue;
-                std::vector<int> hj((size_t)JOB_INTS * n);
+                // the job table through the page-locked block: the stream
+                // is synchronised before the block is written again or freed
+                int *hj = (int *)pinned_get(c, sizeof(int) * JOB_INTS * (size_t)n);
+                if (!hj) return set_err(c, FL_ERR_NOMEM, "page-locked host allocation failed");
                 for (int k = 0; k < n; ++k)
-                    std::memcpy(&hj[(size_t)JOB_INTS * k], jobs[l][sel[l][pos[l] + k]].v, sizeof(int) * JOB_INTS);
-                if ((e = hip_check(c, hipMemcpyAsync(djob, hj.data(), sizeof(int) * hj.size(), hipMemcpyHostToDevice, st),
+                    std::memcpy(hj + (size_t)JOB_INTS * k, jobs[l][sel[l][pos[l] + k]].v, sizeof(int) * JOB_INTS);
+                if ((e = hip_check(c, hipMemcpyAsync(djob, hj, sizeof(int) * JOB_INTS * (size_t)n, hipMemcpyHostToDevice,
+                                                     st),
                                    "upload jobs")))
                     return e;
-                if ((e = hip_check(c, hipStreamSynchronize(st), "sync"))) return e;
                 NoiseBatch nbt;
                 nbt.type = np[l].noise;
                 nbt.seed = np[l].seed;
@@ -1082,24 +1092,36 @@ fl_status fl_loops_stochastic_multi(fl_ctx **ctxs, int nctx, const fl_noise_para
             if ((e = hip_check(c0, hipStreamSynchronize(st), "stochastic batch"))) return e;
         }
     }
-    // L = acc0 / n_lp + acc1 / n_hp
+    // L = acc0 / n_lp + acc1 / n_hp, formed on the device; host results
+    // leave through the context's page-locked block (one DMA per lattice)
+    size_t hbytes = 0;
+    for (int l = 0; l < nctx; ++l) hbytes += sizeof(double2) * nacc[l];
+    unsigned char *stage = nullptr;
+    if (where != FL_DEVICE && hbytes) {
+        stage = (unsigned char *)pinned_get(c0, hbytes);
+        if (!stage) return set_err(c0, FL_ERR_NOMEM, "page-locked host allocation failed");
+    }
+    size_t off = 0;
     for (int l = 0; l < nctx; ++l) {
         fl_ctx *c = ctxs[l];
-        std::vector<double> a0(2 * nacc[l]), a1(2 * nacc[l]);
-        if ((e = hip_check(c, hipMemcpyAsync(a0.data(), acc0[l], sizeof(double2) * nacc[l], hipMemcpyDeviceToHost, st),
-                           "download")))
-            return e;
-        if ((e = hip_check(c, hipMemcpyAsync(a1.data(), acc1[l], sizeof(double2) * nacc[l], hipMemcpyDeviceToHost, st),
-                           "download")))
-            return e;
-        if ((e = hip_check(c, hipStreamSynchronize(st), "sync"))) return e;
         const double w0 = np[l].n_lp > 0 ? 1.0 / np[l].n_lp : 0.0, w1 = np[l].n_hp > 0 ? 1.0 / np[l].n_hp : 0.0;
-        for (size_t k = 0; k < 2 * nacc[l]; ++k) a0[k] = a0[k] * w0 + a1[k] * w1;
-        if ((e = hip_check(c, hipMemcpyAsync(Lout[l], a0.data(), sizeof(double2) * nacc[l],
-                                             where == FL_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost, st),
+        launch_tsm_combine((double *)acc0[l], (const double *)acc1[l], w0, w1, 2LL * (long long)nacc[l], st);
+        if ((e = hip_check(c, hipGetLastError(), "combine"))) return e;
+        const size_t nb = sizeof(double2) * nacc[l];
+        if ((e = hip_check(c, hipMemcpyAsync(stage ? (void *)(stage + off) : (void *)Lout[l], acc0[l], nb,
+                                             stage ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st),
                            "copy out")))
             return e;
-        if ((e = hip_check(c, hipStreamSynchronize(st), "sync"))) return e;
+        off += nb;
+    }
+    if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
+    if (stage) {
+        off = 0;
+        for (int l = 0; l < nctx; ++l) {
+            const size_t nb = sizeof(double2) * nacc[l];
+            std::memcpy(Lout[l], stage + off, nb);
+            off += nb;
+        }
     }
     if (worst != FL_OK) return set_err(c0, worst, "some solves did not reach their tolerance (fl_last_stats)");
     return FL_OK;

@@ -498,6 +498,16 @@ __global__ void k_dot64(const double2 *a, const double2 *b, long long n, double 
     if (threadIdx.x == 0) ((double2 *)out2)[blockIdx.x] = make_double2(re[0], im[0]);  // one store, ends the kernel
 }
 
+// the two-estimator combination L = w0 a0 + w1 a1 (Sec. II, truncated
+// solver method) in place of a0, reals of complex entries; each product is
+// rounded before the sum (no fused multiply-add).  One element per thread,
+// so the store ends the kernel.
+__global__ void k_tsm_combine(double *a0, const double *a1, double w0, double w1, long long n)
+{
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) a0[i] = __dadd_rn(__dmul_rn(a0[i], w0), __dmul_rn(a1[i], w1));
+}
+
 inline unsigned nblk(long long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -562,6 +572,11 @@ void launch_force(const ForceArgs &a, hipStream_t s)
 {
     long long n = 8LL * a.g.Vh;
     if (a.nrhs) hipLaunchKernelGGL(k_force, dim3(nblk(n, 128)), dim3(128), 0, s, a);
+}
+
+void launch_tsm_combine(double *a0, const double *a1, double w0, double w1, long long n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_tsm_combine, dim3(nblk(n)), dim3(256), 0, s, a0, a1, w0, w1, n);
 }
 
 void launch_dot64(const double2 *a, const double2 *b, long long n, double *out2, hipStream_t s)

@@ -216,6 +216,7 @@ struct StochContractArgs {
     double2 *acc0, *acc1;     // accumulators [ngamma][nt][Vs] for targets 0 and 1
 };
 void launch_stoch_contract(const StochContractArgs &a, hipStream_t s);
+void launch_tsm_combine(double *a0, const double *a1, double w0, double w1, long long n, hipStream_t s);
 
 // gradient kernels
 struct ChiArgs {

@@ -418,7 +418,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
     // 16^3x32 at kappa 0.1596: 15 instead of 17 replacements per system),
     // often on fast ones (a replacement far behind its trigger costs
     // iterations)
-    int chunk = trunc ? 2 : (solver == FL_SOLVER_CGNR ? 16 : 8);
+    int chunk = trunc ? 4 : (solver == FL_SOLVER_CGNR ? 16 : 8);
     std::vector<double> rr_prev(nsys, 0.0);
     std::vector<int> act_start(nsys, 0);
     active_count.assign(sb.nlat, 0);
@@ -486,6 +486,26 @@ fl_status Solver::run(std::vector<SysResult> &res)
                     fmin = std::min(fmin, std::pow(hst[k].rr / rr_prev[k], 1.0 / nch));
             if (fmin < 1.0)
                 chunk = std::min(16, std::max(2, (int)std::floor(std::log(delta * delta) / std::log(fmin))));
+        }
+        if (trunc && any_active) {
+            // truncated solves stop on the device (a system leaves the active
+            // set in the scalar step that meets its residual), so the host
+            // only has to notice that all have stopped: the next check comes
+            // when the slowest system still iterating is expected to stop
+            // (launches after that run with no active system and do no work)
+            double need = 0.0;
+            bool est = false;
+            const int nch = chunk;
+            for (int k = 0; k < nsys; ++k)
+                if (act_start[k] && hact[k] && !done[k] && rr_prev[k] > 0 && hst[k].rr > 0 &&
+                    hst[k].rr < rr_prev[k]) {
+                    const double f = std::pow(hst[k].rr / rr_prev[k], 1.0 / nch);
+                    if (f < 1.0) {
+                        need = std::max(need, std::log(hst[k].stop2 / hst[k].rr) / std::log(f));
+                        est = true;
+                    }
+                }
+            if (est) chunk = std::min(16, std::max(2, (int)std::ceil(need)));
         }
 
         bool any_upd = false, any_restart = false;
