@@ -64,6 +64,13 @@ def profiled_traffic(prec):
     return float(m_t.group(1))
 
 
+def window(tag, t0_ns):
+    """Log a monotonic-clock interval (the clock of rocprofv3's kernel
+    timestamps) ending now, so that a kernel trace of the run can be cut to
+    the workload it brackets."""
+    log(f"[bench] window {tag} {t0_ns} {time.monotonic_ns()}")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -222,6 +229,7 @@ def main():
         log(f"[bench] warmup step {k}: {time.perf_counter() - t0:.2f}s")
     lat.profile_enable(fl.PROF_DSLASH, True)
     torch.cuda.synchronize()
+    w_steps = time.monotonic_ns()
     t0 = time.perf_counter()
     loops = []
     solve_stats = []
@@ -232,6 +240,7 @@ def main():
             f"({lat.profile_read(fl.PROF_DSLASH)['launches']} hopping launches so far)")
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
+    window("timed_steps", w_steps)
     # every timed solve must have met the stopping rule on the full operator
     conv = np.concatenate([st["converged"] for st in solve_stats])
     resid = np.concatenate([st["true_resid"] for st in solve_stats])
@@ -311,10 +320,12 @@ def main():
         pe = fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, solver=solver, batch=768)
         le.loops_exact([1], gam, pe)  # warm-up (one timeslice)
         torch.cuda.synchronize()
+        w0 = time.monotonic_ns()
         t_e = time.perf_counter()
         le.loops_exact([0], gam, pe)
         torch.cuda.synchronize()
         t_e = time.perf_counter() - t_e
+        window("exact_8x8x8x16_timeslice", w0)
         ns = 12 * We["dims"][0] * We["dims"][1] * We["dims"][2]
         extras["exact_loops_8x8x8x16_one_timeslice"] = {
             "point_sources": ns, "seconds": round(t_e, 3), "solves_per_s": round(ns / t_e, 1),
@@ -333,11 +344,14 @@ def main():
                              t_begin=0, t_end=Wt["dims"][3]) for (_, Wt) in lts]
         lp_t = fl.SolverParams(tol=1e-3, truncated=True)
         hp_t = fl.SolverParams(tol=1e-12)
+        fl.loops_stochastic_multi([lt for (lt, _) in lts], qs, gam, lp_t, hp_t)  # warm-up (allocations)
         torch.cuda.synchronize()
+        w0 = time.monotonic_ns()
         t_t = time.perf_counter()
         fl.loops_stochastic_multi([lt for (lt, _) in lts], qs, gam, lp_t, hp_t)
         torch.cuda.synchronize()
         t_t = time.perf_counter() - t_t
+        window("uneven_tsm_batch", w0)
         extras["uneven_tsm_batch_8^4_12^3x24_16^3x32"] = {
             "lp_solves": 3 * 64, "hp_solves": 3 * 4, "lp_tol": 1e-3, "hp_tol": 1e-12, "seconds": round(t_t, 3)}
         log(f"[bench] uneven TSM batch (3 lattices, 64 LP + 4 HP each): {t_t:.2f} s")
