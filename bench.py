@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--fp64-rhs", type=int, default=4, help="single-RHS FP64 GPU solves for the reference rate")
     ap.add_argument("--timed-only", action="store_true",
                     help="run only the warmup and timed steps (for kernel profiles of the timed region)")
+    ap.add_argument("--metrics-jsonl", default="",
+                    help="append one JSON line per timed solve (iterations, replacements, residual) to this file")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device to device before the timed steps (counter calibration)")
     args = ap.parse_args()
@@ -254,6 +256,10 @@ def main():
                       "iterations_mean": round(float(iters.mean()), 1), "iterations_max": int(iters.max()),
                       "fp64_updates_mean": round(float(upd.mean()), 2)}
     log(f"[bench] timed solves: {solves_summary}")
+    if args.metrics_jsonl:
+        for k, st in enumerate(solve_stats):
+            fl.append_jsonl(args.metrics_jsonl, fl.stats_records(st, step=k, workload="stochastic_16x16x16x32",
+                                                                 prec=args.prec, solver=args.solver))
     prof = lat.profile_read(fl.PROF_DSLASH)
     lat.profile_enable(fl.PROF_DSLASH, False)
     value = solves_per_step * args.steps / T

@@ -611,3 +611,62 @@ def _loop_fn_class():
 def loops_exact_autograd(kappa, U, lattice, t0, gammas, params: SolverParams = None):
     """Differentiable exact loops (see LoopFn)."""
     return _loop_fn_class().apply(kappa, U, lattice, t0, gammas, params or SolverParams())
+
+
+def stats_records(stats, **fields):
+    """One dict per solve of a per-solve statistics result (Lattice.last_stats()):
+    index, iterations, FP64 replacements, converged, |Dx-b|/|b| on the full
+    operator and the batch's seconds, each with the given extra fields."""
+    n = len(stats["iters"])
+    return [dict(fields, solve=k, iters=int(stats["iters"][k]), updates=int(stats["updates"][k]),
+                 converged=bool(stats["converged"][k]), true_resid=float(stats["true_resid"][k]),
+                 seconds=float(stats["seconds"][k])) for k in range(n)]
+
+
+def append_jsonl(path, records):
+    """Append records (dicts) to path as JSON lines, one write per call."""
+    import json
+    txt = "".join(json.dumps(r, sort_keys=True) + "\n" for r in records)
+    with open(path, "a") as f:
+        f.write(txt)
+
+
+def loop_key(U, kappa, gammas, params: SolverParams):
+    """Identity of an exact-loop computation: SHA-256 (first 16 hex digits) of
+    the links, kappa, the insertions and the solver parameters."""
+    import hashlib
+    h = hashlib.sha256()
+    a = U.detach().cpu().numpy() if _is_torch(U) else np.asarray(U)
+    h.update(np.ascontiguousarray(a, dtype=np.complex128).tobytes())
+    h.update(repr((float(kappa), [int(g) for g in gammas],
+                   (params.solver, params.tol, params.max_iter, params.inner_prec, params.gauge_reals,
+                    params.delta, bool(params.truncated), params.max_outer))).encode())
+    return h.hexdigest()[:16]
+
+
+def loops_exact_checkpointed(lattice, t0s, gammas, params: SolverParams, directory, key, log=None):
+    """Exact loops L[ngamma][nt][Vs] of several timeslices, one solving call
+    per timeslice, each timeslice's result kept as <directory>/<key>_t<t>.npy
+    (written to a temporary file and renamed).  A timeslice whose file exists
+    is loaded instead of solved again, so an interrupted run resumes where it
+    stopped; key names the computation (loop_key of the links, kappa, the
+    insertions and the solver parameters)."""
+    os.makedirs(directory, exist_ok=True)
+    out = []
+    for t in t0s:
+        path = os.path.join(directory, f"{key}_t{int(t)}.npy")
+        if os.path.exists(path):
+            L = np.load(path)
+            if log:
+                log(f"timeslice {t}: loaded {path}")
+        else:
+            L = lattice.loops_exact([int(t)], gammas, params)
+            if _is_torch(L):
+                L = L.cpu().numpy()
+            tmp = f"{path}.{os.getpid()}.tmp.npy"
+            np.save(tmp, L)
+            os.replace(tmp, path)
+            if log:
+                log(f"timeslice {t}: solved, saved {path}")
+        out.append(L[:, 0])
+    return np.stack(out, axis=1)
