@@ -306,12 +306,12 @@ fl_status fl_bench_dslash(fl_ctx *ctx, int prec, int gauge_reals, int nrhs, int 
  * workgroup's links, 3 (FL_PREC_H16 only) as 2 with the hop computed on the
  * stored 16-bit integers (packed int16 spin projection, exact int16 dot
  * products for the colour product, links staged at half scale in the two
- * forms those products need), 4 (FL_PREC_H16 only) as 3 without neighbour
- * windows, every neighbour spinor loaded two directions before its use,
- * -1 the built-in choice (4 for FL_PREC_H16, 1 for FP64, 2
- * otherwise, each falling back to a smaller mode when its LDS does not fit).
- * rt = 0 restores the built-in workgroup size.  FL_ERR_ARG for out-of-range
- * values or lds 3, 4 with another precision. */
+ * forms those products need), 4 the workgroup's links only, no neighbour
+ * windows (for FL_PREC_H16 the packed hop of 3, every neighbour spinor
+ * loaded two directions before its use), -1 the built-in choice (1 for
+ * FP64, 4 otherwise, falling back to a smaller mode when its LDS does not
+ * fit).  rt = 0 restores the built-in workgroup size.
+ * FL_ERR_ARG for out-of-range values or lds 3 with another precision. */
 fl_status fl_set_tile(fl_ctx *ctx, int prec, int gauge_reals, int rt, int group, int lds);
 
 /* Autotuner: time the hopping kernel for nrhs right-hand sides over the

@@ -418,12 +418,16 @@ void dslash_config(const fl_ctx *c, LinkFormat fmt, DslashArgs &a)
     }
     a.wsmax = (ws + 3) & ~3;  // 16-byte aligned windows for every site format
     int mode = c->tune_lds[fmt];
-    // built-in (measured at 16^3x32): FP32 windows and staged links, FP64
-    // windows only, 16-bit fields the packed hop with staged links and no
-    // windows; a mode that does not fit the LDS falls back to the next
-    if (mode < 0) mode = fmt == LINK_F64_R18 ? 1 : (fmt == LINK_Q16_R12 ? 4 : 2);
-    if (mode >= 3 && fmt != LINK_Q16_R12) mode = 2;  // the packed integer hop is for 16-bit fields only
-    while (mode > 0 && dslash_lds_bytes(fmt, a.B.RT, a.wsmax, mode) > c->max_lds) --mode;
+    // built-in (measured at 16^3x32): FP64 windows only; every other format
+    // staged links and no windows (16-bit fields: the packed hop; FP32 and
+    // bf16: 1611 and 1567 us against 1708 and 1651 us with windows, whose
+    // LDS held a CU to one workgroup); a mode that does not fit the LDS
+    // falls back to a smaller one
+    if (mode < 0) mode = fmt == LINK_F64_R18 ? 1 : 4;
+    if (mode == 3 && fmt != LINK_Q16_R12) mode = 2;  // the packed integer hop with windows: 16-bit fields only
+    // a mode whose staging does not fit falls back: 4 -> 2 -> 1 -> 0 (3 -> 2 -> ...)
+    while (mode > 0 && dslash_lds_bytes(fmt, a.B.RT, a.wsmax, mode) > c->max_lds)
+        mode = (mode == 4 && fmt != LINK_Q16_R12) ? 2 : mode - 1;
     a.lds = mode;
 }
 
@@ -1439,8 +1443,8 @@ fl_status fl_bench_dslash(fl_ctx *c, int prec, int gauge_reals, int nrhs, int nr
     if ((e = check_ready(c))) return e;
     LinkFormat fmt;
     if ((e = fmt_of(c, prec, gauge_reals, &fmt))) return e;
-    if (lds < -1 || lds > 4 || (lds >= 3 && fmt != LINK_Q16_R12))
-        return set_err(c, FL_ERR_ARG, "lds must be -1, 0, 1 or 2 (3, 4: 16-bit fields only)");
+    if (lds < -1 || lds > 4 || (lds == 3 && fmt != LINK_Q16_R12))
+        return set_err(c, FL_ERR_ARG, "lds must be -1, 0, 1, 2 or 4 (3: 16-bit fields only)");
     return bench_impl(c, fmt, nrhs, nrep, nsets, rt, group, lds, ms_per_launch, bytes_per_launch);
 }
 
@@ -1460,7 +1464,7 @@ fl_status fl_set_tile(fl_ctx *c, int prec, int gauge_reals, int rt, int group, i
         fmt = LINK_Q16_R12;
     else
         return set_err(c, FL_ERR_ARG, "unsupported precision / link storage");
-    if (lds >= 3 && fmt != LINK_Q16_R12) return set_err(c, FL_ERR_ARG, "lds 3 and 4 need 16-bit fields");
+    if (lds == 3 && fmt != LINK_Q16_R12) return set_err(c, FL_ERR_ARG, "lds 3 needs 16-bit fields");
     c->tune_rt[fmt] = rt;
     c->tune_g[fmt] = group;
     c->tune_lds[fmt] = lds;
@@ -1479,9 +1483,9 @@ fl_status fl_autotune(fl_ctx *c, int prec, int gauge_reals, int nrhs, int *rt_ou
     const int maxrt = fmt == LINK_F64_R18 ? 8 : 16;
     double best = 1e300;
     int brt = 0, bg = 0, bl = 0;
-    const int maxlds = fmt == LINK_Q16_R12 ? 4 : 2;
-    for (int lds = 0; lds <= maxlds; ++lds)
+    for (int lds = 0; lds <= 4; ++lds)
         for (int rt = 1; rt <= maxrt; rt *= 2) {
+            if (lds == 3 && fmt != LINK_Q16_R12) break;
             if (rt > 1 && rt / 2 >= nrhs) break;
             int nrb = (nrhs + rt - 1) / rt;
             for (int g = 1;; g *= 2) {

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(512) void k_dslash_h16_wide(DslashArgs a)
     }
 }
 
-template <typename S, class LK, bool SLINK>
+template <typename S, class LK, bool SLINK, bool WIN = true>
 struct LdsSrc {
     typedef typename SpinorFmt<S>::R R;
     static constexpr bool PACKED_I16 = false;
@@ -197,7 +197,7 @@ struct LdsSrc {
     template <int MU>
     __device__ __forceinline__ R spinor(int i, cx<R> s[12]) const
     {
-        if (MU < 2)
+        if (WIN && MU < 2)
             return SpinorFmt<S>::lds_load_raw(win, wsmax, i - wlo, s);
         else
             return SpinorFmt<S>::load_raw(in, Vh, i, s);
@@ -264,7 +264,9 @@ __device__ __forceinline__ int back_neighbour(const LatGeom &g, const Coord &c, 
 
 // SLINK: links staged in LDS; PK (16-bit fields only, with SLINK): the
 // packed integer hop with half-scale staged links;
-// NOWIN: no neighbour windows (x/y neighbours from memory like z/t)
+// NOWIN: no neighbour windows (x/y neighbours from memory like z/t); with
+// SLINK and without PK the LDS holds the staged links only, so that more
+// workgroups fit a CU than with the windows
 template <typename S, class LK, bool DAG, int EPI, bool SLINK, bool PK = false, bool NOWIN = false>
 __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024) void k_dslash_lds(DslashArgs a)
 {
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
             else
                 hop_site<DAG, R>(g, a.par, T.site, c, src, acc);
         } else {
-            LdsSrc<S, LK, SLINK> src;
+            LdsSrc<S, LK, SLINK, !NOWIN> src;
             src.in = ibuf;
             src.gauge = gbuf;
             src.Vh = Vh;
@@ -374,9 +376,12 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
 template <typename S, class LK>
 size_t dslash_lds_bytes_t(int RT, int wsmax, int lds)
 {
+    // modes: 1 windows, 2 windows + staged links, 3 (16-bit) windows + packed
+    // staged links, 4 staged links only (packed for 16-bit fields)
+    constexpr bool Q16 = std::is_same<LK, LinkQ16R12>::value;
     size_t b = lds == 4 ? 0 : (size_t)RT * SpinorFmt<S>::SITE_BYTES * wsmax;
-    if (lds == 2) b += (size_t)8 * LK::SNC * FL_WAVE * sizeof(typename LK::SV);
-    if constexpr (std::is_same<LK, LinkQ16R12>::value)
+    if (lds == 2 || (lds == 4 && !Q16)) b += (size_t)8 * LK::SNC * FL_WAVE * sizeof(typename LK::SV);
+    if constexpr (Q16)
         if (lds >= 3) b += (size_t)8 * LK::PK_SNC * FL_WAVE * sizeof(typename LK::SV);
     return b;
 }
@@ -397,6 +402,9 @@ void launch_one(const DslashArgs &a, dim3 grid, dim3 block, hipStream_t s)
                 hipLaunchKernelGGL((k_dslash_lds<S, LK, DAG, EPI, true, true, true>), grid, block, shm, s, a);
                 return;
             }
+        } else if (a.lds == 4) {
+            hipLaunchKernelGGL((k_dslash_lds<S, LK, DAG, EPI, true, false, true>), grid, block, shm, s, a);
+            return;
         }
         if (a.lds >= 2)
             hipLaunchKernelGGL((k_dslash_lds<S, LK, DAG, EPI, true>), grid, block, shm, s, a);

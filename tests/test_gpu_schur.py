@@ -27,8 +27,8 @@ pytestmark = pytest.mark.gpu
 KAPPA = 0.2
 TOL = {0: 1e-13, 1: 1e-5, 2: 5e-3, 3: 1e-3}
 # (precision, link reals, lds mode); -1 is the built-in choice
-CASES = [(0, 18, -1), (0, 18, 0), (1, 18, 2), (1, 12, 0), (1, 12, 1), (1, 12, 2), (2, 12, 2),
-         (3, 12, 0), (3, 12, 1), (3, 12, 2), (3, 12, 3), (3, 12, 4)]
+CASES = [(0, 18, -1), (0, 18, 0), (0, 18, 4), (1, 18, 2), (1, 18, 4), (1, 12, 0), (1, 12, 1), (1, 12, 2),
+         (1, 12, 4), (2, 12, 2), (2, 12, 4), (3, 12, 0), (3, 12, 1), (3, 12, 2), (3, 12, 3), (3, 12, 4)]
 
 
 @pytest.fixture(scope="module")
