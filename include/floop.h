@@ -178,7 +178,9 @@ const char *fl_version(void);
  * even extents >= 2; bc_t = +1 (periodic) or -1 (antiperiodic) in time. */
 fl_status fl_create(fl_ctx **ctx, int device, const int dims[4], int bc_t);
 
-/* Release every device buffer of the context.  NULL is accepted. */
+/* Release every device buffer of the context and its page-locked host
+ * staging block (grown on demand by the solving calls for the per-system
+ * solver state, masks, norms and host results).  NULL is accepted. */
 fl_status fl_destroy(fl_ctx *ctx);
 
 /* Stream for all later device work of the context (hipStream_t passed as
