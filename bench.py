@@ -12,9 +12,11 @@ arithmetic on 16-bit fixed-point vectors and links, FP64 reliable updates;
 Eq. (loop stochastic) for Gamma = 1, g5, g1..g4.
 
 Prints one JSON line:  value = diluted solves per second (whole job).
-roofline: the hopping kernel of the iteration (events around every launch
-on the library's stream), algorithmic bytes = 8 links + input + output per
-site and right-hand side.  cpu_baseline: the FP64 oracle solving one of the
+roofline: the dominant kernel of the step, the hopping launch with the
+fused epilogue that ends each CGNR iteration (events around every launch on
+the library's stream; algorithmic bytes = 8 links per site + its input,
+its two own-site operands and its output per site and right-hand side);
+roofline_first_hop: the iteration's first hop, H_oe (input + output).  cpu_baseline: the FP64 oracle solving one of the
 same diluted sources on the host cores.
 """
 import argparse
@@ -37,11 +39,16 @@ FP32_PEAK_TFLOPS = 157.3
 FLOP_PER_SITE = 1320  # standard count of one hopping term per output site and right-hand side
 SITE_BYTES = {"f32": 96, "bf16": 96, "h16": 52}
 LINK_BYTES = {"f32": 48, "bf16": 24, "h16": 24}
-# rocprofv3 counter summary of the hopping kernel timed here (FETCH_SIZE and
-# WRITE_SIZE passes, scaled by a copy kernel of known size); its traffic is
+# rocprofv3 counter summary of the hopping kernels timed here (FETCH_SIZE and
+# WRITE_SIZE passes, scaled by a copy kernel of known size); their traffic is
 # reported only while the kernel sources still hash to the recorded value
 def traffic_profile(prec):
     return os.path.join(ROOT, "profiles", f"hopping_{prec}r12_stoch_16x16x16x32.md")
+
+
+# the two timed hopping launches: library profiling slot and the vector
+# fields each reads or writes once per site and right-hand side (CGNR)
+HOPS = {"first_hop": (0, 2), "end_hop": (1, 4)}
 
 
 def kernel_source_hash():
@@ -50,15 +57,17 @@ def kernel_source_hash():
     return build.source_hash()
 
 
-def profiled_traffic(prec):
-    """HBM bytes per launch from the committed counter summary, or None if the
-    summary is missing or was taken on other kernel sources."""
+def profiled_traffic(prec, hop="first_hop"):
+    """HBM bytes per launch of one timed hop from the committed counter
+    summary, or None if the summary is missing or was taken on other kernel
+    sources."""
     try:
         txt = open(traffic_profile(prec)).read()
     except OSError:
         return None
+    key = "traffic_bytes_per_launch" + ("" if hop == "first_hop" else "_" + hop)
     m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
-    m_t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_t = re.search(key + r":\s*([0-9.eE+]+)", txt)
     if not m_hash or not m_t or m_hash.group(1) != kernel_source_hash():
         return None
     return float(m_t.group(1))
@@ -230,6 +239,7 @@ def main():
         step(1000 + k)
         log(f"[bench] warmup step {k}: {time.perf_counter() - t0:.2f}s")
     lat.profile_enable(fl.PROF_DSLASH, True)
+    lat.profile_enable(fl.PROF_DSLASH_END, True)
     torch.cuda.synchronize()
     w_steps = time.monotonic_ns()
     t0 = time.perf_counter()
@@ -260,13 +270,21 @@ def main():
         for k, st in enumerate(solve_stats):
             fl.append_jsonl(args.metrics_jsonl, fl.stats_records(st, step=k, workload="stochastic_16x16x16x32",
                                                                  prec=args.prec, solver=args.solver))
-    prof = lat.profile_read(fl.PROF_DSLASH)
-    lat.profile_enable(fl.PROF_DSLASH, False)
+    profs = {}
+    for name, (slot, _) in HOPS.items():
+        pr = lat.profile_read(slot)
+        lat.profile_enable(slot, False)
+        pr["avg_us"] = pr["ms"] * 1e3 / max(1, pr["launches"])
+        pr["achieved"] = pr["bytes"] / (pr["ms"] * 1e-3) / 1e9 if pr["ms"] > 0 else 0.0
+        profs[name] = pr
+    # the roofline is reported for the kernel that takes the most time
+    dominant = max(profs, key=lambda h: profs[h]["ms"])
+    prof = profs["first_hop"]
+    achieved, avg_us = prof["achieved"], prof["avg_us"]
     value = solves_per_step * args.steps / T
-    achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
-    avg_us = prof["ms"] * 1e3 / max(1, prof["launches"])
     log(f"[bench] {value:.1f} solves/s; hopping kernel {prof['launches']} launches, avg {avg_us:.1f} us, "
-        f"{achieved:.0f} GB/s")
+        f"{achieved:.0f} GB/s; end hop avg {profs['end_hop']['avg_us']:.1f} us, "
+        f"{profs['end_hop']['achieved']:.0f} GB/s; dominant: {dominant}")
 
     # disconnected two-point function (Eq. all_dis_corr) from the timed steps
     # loops: two independent noise vectors, 33 momenta with |n|^2 <= 3, all
@@ -310,7 +328,11 @@ def main():
     if args.timed_only:
         print(json.dumps({"metric": METRIC, "value": round(value, 3), "unit": "solves/s", "steps": args.steps,
                           "hopping_kernel": {"launches": prof["launches"], "avg_launch_us": round(avg_us, 2),
-                                             "achieved_GBs": round(achieved, 1)}}), flush=True)
+                                             "achieved_GBs": round(achieved, 1)},
+                          "end_hop_kernel": {"launches": profs["end_hop"]["launches"],
+                                             "avg_launch_us": round(profs["end_hop"]["avg_us"], 2),
+                                             "achieved_GBs": round(profs["end_hop"]["achieved"], 1)}}),
+              flush=True)
         return
     # the other workloads of the path, timed once each outside the timed region:
     # exact loops of one whole timeslice, the uneven truncated-solver batch of
@@ -404,19 +426,31 @@ def main():
     if not args.no_cpu_baseline:
         cpu, loop_err = cpu_baseline(U, b, x_mp, dims, bc, kappa, gam)
 
-    bytes_per_launch = prof["bytes"] / max(1, prof["launches"])
-    traffic = profiled_traffic(args.prec)
-    # site x right-hand-side pairs per launch from the algorithmic bytes
-    # (8 links per site once, input and output spinor per pair)
     Vh = S.volume(dims) // 2
-    pairs = (bytes_per_launch - 8 * LINK_BYTES[args.prec] * Vh) / (2 * SITE_BYTES[args.prec])
-    tflops = FLOP_PER_SITE * pairs / (avg_us * 1e-6) / 1e12 if avg_us > 0 else 0.0
-    # every storage format's hopping kernel is limited by the memory system
-    # (for 16-bit storage its HBM-side traffic runs at ~83 % of the plain-copy
-    # rate with the vector units ~2/3 busy); the FP32 rate is reported beside it
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "fp32_TFLOPs": round(tflops, 2),
-            "fp32_frac": round(tflops / FP32_PEAK_TFLOPS, 4)}
+
+    def hop_roof(name):
+        # site x right-hand-side pairs per launch from the algorithmic bytes
+        # (8 links per site once, the hop's fields once per pair); the FP32
+        # rate counts the hopping term's flops only
+        pr, fields = profs[name], HOPS[name][1]
+        if name == "end_hop" and args.solver != "cgnr":
+            fields = 3  # BiCGStab: t = Dhat s reads s at the site
+        bpl = pr["bytes"] / max(1, pr["launches"])
+        pairs = (bpl - 8 * LINK_BYTES[args.prec] * Vh) / (fields * SITE_BYTES[args.prec])
+        tflops = FLOP_PER_SITE * pairs / (pr["avg_us"] * 1e-6) / 1e12 if pr["avg_us"] > 0 else 0.0
+        label = {"first_hop": "hopping term H_oe of Dhat p (no epilogue)",
+                 "end_hop": "hopping term H_eo of Dhat^+ q with the fused update z -= alpha (q + c H q') "
+                            "and |z|^2 (reads q and z at the site)" if args.solver == "cgnr" else
+                            "hopping term H_eo of Dhat s with <t, s> and |t|^2 (reads s at the site)"}[name]
+        # every storage format's hopping kernel is limited by the memory
+        # system; the FP32 rate is reported beside it
+        return {"kernel": f"{label}, {args.prec} storage, 12-real links, iteration launches",
+                "bound": "hbm", "achieved": round(pr["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(pr["achieved"] / HBM_PEAK_GBS, 4), "fp32_TFLOPs": round(tflops, 2),
+                "fp32_frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": profiled_traffic(args.prec, name),
+                "avg_launch_us": round(pr["avg_us"], 2), "launches": pr["launches"],
+                "share_of_step": round(pr["ms"] * 1e-3 / T, 4), "algorithmic_bytes_per_launch": round(bpl)}
+
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -447,14 +481,8 @@ def main():
             "rt": args.rt,
             "parallelism": "single GPU",
         },
-        "roofline": {
-            "kernel": f"hopping term H_oe ({args.prec} storage, 12-real links), iteration launches",
-            **roof,
-            "traffic": traffic,
-            "avg_launch_us": round(avg_us, 2),
-            "launches": prof["launches"],
-            "algorithmic_bytes_per_launch": round(bytes_per_launch),
-        },
+        "roofline": hop_roof(dominant),
+        "roofline_first_hop": hop_roof("first_hop"),
         "iteration_roofline": iteration_roofline(args.solver, args.prec, Vh, float(iters.sum()) / args.steps,
                                                  ITER_HOPS * float(iters.max()), T / args.steps),
         "cpu_baseline": cpu,

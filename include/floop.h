@@ -283,8 +283,15 @@ fl_status fl_loops_grad(fl_ctx *ctx, const int *t0, int nt, const int *gammas, i
  * launch of the named kernel while enabled (kernel ids below).  Reset on
  * enable.  ms: summed event time; launches: count; bytes: summed
  * algorithmic bytes of those launches (links and spinors read once, outputs
- * written once). */
-enum { FL_PROF_DSLASH = 0, FL_PROF_NKERNELS = 4 };
+ * written once, counted for the systems still iterating).
+ *   FL_PROF_DSLASH: the first hop of every Krylov iteration, H_oe of the
+ *     Schur operator applied to the search direction (no epilogue).
+ *   FL_PROF_DSLASH_END: the hop with the fused epilogue that ends the
+ *     operator work of an iteration: for CGNR the second hop of Dhat^+ q
+ *     with z -= alpha (q + c H q') and |z|^2 (reads q and z at the site), for
+ *     truncated CGNR the second hop of Dhat^+ r with |z|^2, for BiCGStab
+ *     the second hop of Dhat s with <t, s> and |t|^2 (reads s at the site). */
+enum { FL_PROF_DSLASH = 0, FL_PROF_DSLASH_END = 1, FL_PROF_NKERNELS = 4 };
 fl_status fl_profile_enable(fl_ctx *ctx, int kernel, int enable);
 fl_status fl_profile_read(fl_ctx *ctx, int kernel, double *ms, long long *launches,
                           double *bytes);

@@ -73,7 +73,7 @@ struct Solver {
     double lo_bytes_per_site_rhs() const { return (double)vec_site_bytes(vf); }
 
     void dslash(LinkFormat f, bool lo, int par, const MF &in, const MF &out, const MF *x, const MF *y,
-                double ca, const double *cbv, int epi, int slot0, const int *msk, bool dag, bool prof)
+                double ca, const double *cbv, int epi, int slot0, const int *msk, bool dag, int pslot)
     {
         DslashArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -94,9 +94,9 @@ struct Solver {
             a.cb[l] = cbv ? cbv[l] : 1.0;
         }
         dslash_config(c0, f, a);
-        if (prof) prof_begin(c0, FL_PROF_DSLASH);
+        if (pslot >= 0) prof_begin(c0, pslot);
         launch_dslash(f, a, dag, epi, st);
-        if (prof) prof_end(c0, FL_PROF_DSLASH, 0.0);
+        if (pslot >= 0) prof_end(c0, pslot, 0.0);
     }
 
     void blas(VecFormat f, int op, std::initializer_list<const MF *> fields, int flag, int slot0, const int *msk)
@@ -137,21 +137,23 @@ struct Solver {
 
     double neg_k2[FL_MAXLAT], pos_k2[FL_MAXLAT];
 
-    // Dhat (or Dhat^+) applied in the iteration precision: out = in - k^2 H_eo H_oe in
-    void schur_lo(const MF &in, const MF &out, int epi_extra, const MF *y, int slot0, bool dag)
+    // Dhat (or Dhat^+) applied in the iteration precision: out = in - k^2 H_eo H_oe in;
+    // p1, p2: profiling slots of the two hops (-1: none)
+    void schur_lo(const MF &in, const MF &out, int epi_extra, const MF *y, int slot0, bool dag, int p1 = -1,
+                  int p2 = -1)
     {
-        dslash(fmt, true, 1, in, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, dag, !dag);
-        dslash(fmt, true, 0, TMP, out, &in, y, 1.0, neg_k2, EPI_XPAY | epi_extra, slot0, active, dag, false);
+        dslash(fmt, true, 1, in, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, dag, p1);
+        dslash(fmt, true, 0, TMP, out, &in, y, 1.0, neg_k2, EPI_XPAY | epi_extra, slot0, active, dag, p2);
     }
 
     // one BiCGStab iteration for every active system
     void bicg_iteration()
     {
         const VecFormat lf = vf;
-        schur_lo(P, V, EPI_DOTY, &R0, 0, false);                   // v = Dhat p, <r0, v>
+        schur_lo(P, V, EPI_DOTY, &R0, 0, false, FL_PROF_DSLASH);   // v = Dhat p, <r0, v>
         scal(SC_ALPHA, nullptr);
         blas(lf, OP_BICG_S, {&R, &V, &S}, 0, 0, active);          // s = r - alpha v
-        schur_lo(S, T, EPI_DOTX_NORM, nullptr, 0, false);           // t = Dhat s, <t, s>, |t|^2
+        schur_lo(S, T, EPI_DOTX_NORM, nullptr, 0, false, -1, FL_PROF_DSLASH_END);  // t = Dhat s, <t, s>, |t|^2
         scal(SC_OMEGA, nullptr);
         blas(lf, OP_BICG_XR, {&XL, &P, &S, &T, &R, &R0}, 0, 0, active);
         scal(SC_BETA, nullptr);
@@ -170,19 +172,20 @@ struct Solver {
         const VecFormat lf = vf;
         ++stamp;
         // q = Dhat p with |q|^2 (slot 2)
-        dslash(fmt, true, 1, P, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, false, true);
-        dslash(fmt, true, 0, TMP, V, &P, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, false, false);
+        dslash(fmt, true, 1, P, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, false, FL_PROF_DSLASH);
+        dslash(fmt, true, 0, TMP, V, &P, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, false, -1);
         scal(SC_CG_ALPHA, nullptr);
         if (prm.truncated) {
             blas(lf, OP_CG_R, {&R, &V}, 0, 3, active);  // r -= alpha q, |r|^2 -> slot 5
             // z = Dhat^+ r with |z|^2 (slot 2)
-            dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, true, false);
-            dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, true, false);
+            dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, true, -1);
+            dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, active, true,
+                   FL_PROF_DSLASH_END);
         } else {
             // z -= alpha Dhat^+ q in the epilogue of the second hop, with |z|^2 (slot 2)
-            dslash(fmt, true, 1, V, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, true, false);
+            dslash(fmt, true, 1, V, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, active, true, -1);
             dslash(fmt, true, 0, TMP, S, &V, &S, 1.0, neg_k2, EPI_XPAY | EPI_NORM | EPI_CGZ, 0, active, true,
-                   false);
+                   FL_PROF_DSLASH_END);
         }
         scal(SC_CG_BETA, nullptr);
         // x += alpha p (also for a system that stopped in SC_CG_BETA), then p = z + beta p
@@ -217,15 +220,15 @@ struct Solver {
             }
             launch_dslash_h16_wide(a, false, st);                      // t = H_oe xl
             dslash(LINK_F64_R18, false, 0, T64, RH, &RH, &XL, 1.0, pos_k2, EPI_XPAY | EPI_NORM | EPI_SUBY16, 0, msk,
-                   false, false);                                      // rh += k^2 H_eo t - xl
+                   false, -1);                                         // rh += k^2 H_eo t - xl
             blas(vf, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                // xh += xl, xl = 0
         } else {
             blas(vf, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                // xh += xl, xl = 0
             blas(VEC_F64, OP_SUB_HI, {&RH, &BH, &XH}, 0, 0, msk);      // rh = bh - xh
             dslash(LINK_F64_R18, false, 1, XH, T64, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, false,
-                   false);
+                   -1);
             dslash(LINK_F64_R18, false, 0, T64, RH, &RH, nullptr, 1.0, pos_k2, EPI_XPAY | EPI_NORM, 0, msk, false,
-                   false);
+                   -1);
         }
         blas(vf, OP_HI_TO_LO, {&R, &RH, &R0, &P, &XL}, init, 3, msk);
     }
@@ -384,8 +387,8 @@ fl_status Solver::run(std::vector<SysResult> &res)
         return e;
     auto cg_start = [&](const int *msk) {
         // z = Dhat^+ r (|z|^2 -> slot 2); |r|^2 already in slot 5; p = z
-        dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, true, false);
-        dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, msk, true, false);
+        dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, true, -1);
+        dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, msk, true, -1);
         scal(SC_CG_INIT, msk);
         blas(vf, OP_ZERO, {&P}, 0, 0, msk);
         blas(vf, OP_CG_P, {&P, &S}, 0, 0, msk);  // SC_CG_INIT sets beta = 0: p = z
@@ -397,8 +400,8 @@ fl_status Solver::run(std::vector<SysResult> &res)
         // (without it, a replaced residual that has moved away from the
         // recursive one, as it does when an iteration gains a lot between
         // two host checks, derails the recurrence)
-        dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, true, false);
-        dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, msk, true, false);
+        dslash(fmt, true, 1, R, TMP, nullptr, nullptr, 1.0, nullptr, EPI_PLAIN, 0, msk, true, -1);
+        dslash(fmt, true, 0, TMP, S, &R, nullptr, 1.0, neg_k2, EPI_XPAY | EPI_NORM, 0, msk, true, -1);
         blas(vf, OP_DOT, {&S, &P}, 0, 0, msk);
         scal(SC_CG_REZ, msk);
         blas(vf, OP_CG_FIXP, {&P, &S}, 0, 0, msk);
@@ -429,23 +432,30 @@ fl_status Solver::run(std::vector<SysResult> &res)
             if (k >= B.lat[q].sys0) l = q;
         return l;
     };
-    size_t prof_mark = c0->prof[FL_PROF_DSLASH].ev.size();
+    // vector fields each profiled hop reads or writes once per site and
+    // system: the first hop its input and output; the hop that ends the
+    // iteration also its own-site operands (CGNR: q and z; truncated CGNR
+    // and BiCGStab: r resp. s)
+    const int prof_fields[2] = {2, (solver == FL_SOLVER_CGNR && !trunc) ? 4 : 3};
+    size_t prof_mark[2] = {c0->prof[FL_PROF_DSLASH].ev.size(), c0->prof[FL_PROF_DSLASH_END].ev.size()};
     auto account_prof = [&]() {
-        ProfSlot &ps = c0->prof[FL_PROF_DSLASH];
-        if (!ps.on) return;
-        size_t nnew = ps.ev.size() - prof_mark;
-        prof_mark = ps.ev.size();
-        if (!nnew) return;
-        // algorithmic bytes of one hopping launch: every link once per
-        // lattice, plus each input spinor read once and each output written
-        // once for the systems still iterating (counted at the end of the
-        // chunk: a lower bound)
-        double bytes = 0;
-        for (int l = 0; l < B.nlat; ++l) {
-            const double lb = (double)link_bytes(fmt);
-            bytes += 8.0 * lb * B.lat[l].Vh + 2.0 * lo_bytes_per_site_rhs() * B.lat[l].Vh * active_count[l];
+        for (int k = 0; k < 2; ++k) {
+            ProfSlot &ps = c0->prof[k == 0 ? FL_PROF_DSLASH : FL_PROF_DSLASH_END];
+            if (!ps.on) continue;
+            size_t nnew = ps.ev.size() - prof_mark[k];
+            prof_mark[k] = ps.ev.size();
+            if (!nnew) continue;
+            // algorithmic bytes of one hopping launch: every link once per
+            // lattice, plus each field read or written once for the systems
+            // still iterating (counted at the end of the chunk: a lower bound)
+            double bytes = 0;
+            for (int l = 0; l < B.nlat; ++l) {
+                const double lb = (double)link_bytes(fmt);
+                bytes += 8.0 * lb * B.lat[l].Vh +
+                         prof_fields[k] * lo_bytes_per_site_rhs() * B.lat[l].Vh * active_count[l];
+            }
+            ps.bytes += bytes * nnew;
         }
-        ps.bytes += bytes * nnew;
     };
 
     while (ndone < nsys) {

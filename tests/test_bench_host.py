@@ -52,3 +52,13 @@ def test_iteration_roofline_counts_passes_and_links():
     want = (16 * 52 * 65536 * 384 * 400 + 8 * 24 * 65536 * 4 * 400) / 2.5 / 1e9
     assert abs(r["achieved"] - want) <= 0.05 and r["bytes_per_site_and_system_iteration"] == 832
     assert abs(r["frac"] - want / 8000.0) <= 1e-4
+
+
+def test_traffic_of_each_timed_hop(tmp_path, monkeypatch):
+    p = tmp_path / "hopping_h16r12_stoch_16x16x16x32.md"
+    p.write_text(f"    kernel_source_sha256: {bench.kernel_source_hash()}\n"
+                 "    traffic_bytes_per_launch: 3480000000\n    traffic_bytes_per_launch_end_hop: 6110000000\n")
+    monkeypatch.setattr(bench, "traffic_profile", lambda prec: str(p))
+    assert bench.profiled_traffic("h16") == 3.48e9
+    assert bench.profiled_traffic("h16", "first_hop") == 3.48e9
+    assert bench.profiled_traffic("h16", "end_hop") == 6.11e9
