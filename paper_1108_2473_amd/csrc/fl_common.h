@@ -125,8 +125,9 @@ __device__ __forceinline__ v2f buf_ld8(const Buf &b, int voff, int soff)
 }
 
 // CP: cache policy of the store (0: default; ST_STREAM: non-temporal, for
-// results no later access of the same kernel reads)
-enum { ST_STREAM = 2 };
+// results no later access of the same kernel reads); LD_STREAM: the same
+// policy for a load of data no other access of the kernel reads
+enum { ST_STREAM = 2, LD_STREAM = 2 };
 
 template <int CP = 0>
 __device__ __forceinline__ void buf_st16(const Buf &b, v4f v, int voff, int soff)

@@ -27,6 +27,36 @@
 
 namespace {
 
+// An own-site operand of the epilogue (x, y): read once by this kernel, so
+// 16-bit and FP32 fields are loaded non-temporally and leave L2 to the
+// neighbour spinors that other workgroups still read (the dagger hop that
+// updates z, which reads two such fields, at 16^3x32 with 384 right-hand
+// sides: 1235 instead of 1276 us per launch with 16-bit fields, 2223
+// instead of 2358 us with FP32 fields)
+template <typename S, typename R>
+__device__ __forceinline__ void load_once(const Buf &b, int Vh, int i, cx<R> s[12])
+{
+    if constexpr (std::is_same<S, H16>::value) {
+        v4f v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = __builtin_amdgcn_raw_buffer_load_b128(b.r, i * 16, c * Vh * 16, LD_STREAM);
+        const float sc =
+            __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, i * 4, 3 * Vh * 16, LD_STREAM));
+        SpinorFmt<H16>::unpack(v, s);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) s[k] = cx<float>{s[k].re * sc, s[k].im * sc};
+    } else if constexpr (std::is_same<S, float>::value) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const v4f v = __builtin_amdgcn_raw_buffer_load_b128(b.r, i * 16, c * Vh * 16, LD_STREAM);
+            s[2 * c] = cx<float>{v.x, v.y};
+            s[2 * c + 1] = cx<float>{v.z, v.w};
+        }
+    } else {
+        SpinorFmt<S>::load(b, Vh, i, s);
+    }
+}
+
 // S: storage format of the fields (SpinorFmt<S>), arithmetic in SpinorFmt<S>::R.
 // The reductions use the values as stored (after any rounding of the format).
 template <typename S, int EPI, typename R>
@@ -45,7 +75,7 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
     }
     cx<R> out[12], xv[12];
     if (EPI & EPI_XPAY) {
-        F::load(spinor_buf<S>(a.x[T.lat], g.Vh, rhs), g.Vh, T.site, xv);
+        load_once<S, R>(spinor_buf<S>(a.x[T.lat], g.Vh, rhs), g.Vh, T.site, xv);
         const R ca = (R)a.ca[T.lat];
         if (ca == (R)1) {
 #pragma unroll
@@ -61,7 +91,7 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
     if constexpr ((EPI & EPI_CGZ) != 0) {
         // out = y - alpha (x + cb acc), y the field this launch overwrites (own site only)
         cx<R> yv[12];
-        F::load(spinor_buf<S>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, yv);
+        load_once<S, R>(spinor_buf<S>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, yv);
         const R al = (R)a.st[T.sys].alpha[0];
 #pragma unroll
         for (int k = 0; k < 12; ++k) out[k] = cx<R>{fma(-al, out[k].re, yv[k].re), fma(-al, out[k].im, yv[k].im)};
@@ -93,7 +123,7 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
     }
     if (EPI & EPI_DOTY) {
         cx<R> yv[12];
-        F::load(spinor_buf<S>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, yv);
+        load_once<S, R>(spinor_buf<S>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, yv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             cx<R> d = cjmul(yv[k], out[k]);
