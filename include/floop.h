@@ -317,9 +317,9 @@ fl_status fl_bench_dslash(fl_ctx *ctx, int prec, int gauge_reals, int nrhs, int 
  * products for the colour product, links staged at half scale in the two
  * forms those products need), 4 the workgroup's links only, no neighbour
  * windows (for FL_PREC_H16 the packed hop of 3, every neighbour spinor
- * loaded two directions before its use), -1 the built-in choice (1 for
- * FP64, 4 otherwise, falling back to a smaller mode when its LDS does not
- * fit).  rt = 0 restores the built-in workgroup size.
+ * loaded two directions before its use), -1 the built-in choice (4; 1 for
+ * FP64 workgroups of fewer than 4 right-hand sides; falling back to a
+ * smaller mode when its LDS does not fit).  rt = 0 restores the built-in workgroup size.
  * FL_ERR_ARG for out-of-range values or lds 3 with another precision. */
 fl_status fl_set_tile(fl_ctx *ctx, int prec, int gauge_reals, int rt, int group, int lds);
 

@@ -391,15 +391,17 @@ BatchGeom batch_geom(fl_ctx *const *ctx, const int *nrhs, int nlat, int RT, int 
 void tile_shape(const fl_ctx *c, int fmt, int nrhs, int *RT, int *G)
 {
     const int maxrt = fmt == LINK_F64_R18 ? 8 : 16;
-    // built-in choice (measured on the 16^3x32 hopping kernel): 8 right-hand
-    // sides per workgroup (4 in FP64), swept right-hand-side-block by block
-    // so that the stencil's neighbours are still in L2 when reused
-    int rt = c->tune_rt[fmt] > 0 ? c->tune_rt[fmt] : (fmt == LINK_F64_R18 ? 2 : 8);
+    // built-in choice (measured on the 16^3x32 hopping kernel with 384
+    // right-hand sides): 8 right-hand sides per workgroup, swept
+    // right-hand-side-block by block so that the stencil's neighbours are
+    // still in L2 when reused (FP64 with staged links: 3483 us per launch,
+    // against 4391 us for 2 right-hand sides per workgroup with windows)
+    int rt = c->tune_rt[fmt] > 0 ? c->tune_rt[fmt] : 8;
     // no more waves per workgroup than right-hand sides (next power of two)
     int cap = 1;
     while (cap < nrhs && cap < maxrt) cap *= 2;
     *RT = std::max(1, std::min(std::min(rt, maxrt), cap));
-    *G = c->tune_g[fmt] > 0 ? c->tune_g[fmt] : (fmt == LINK_F64_R18 ? 2 : 1);
+    *G = c->tune_g[fmt] > 0 ? c->tune_g[fmt] : 1;
 }
 
 void dslash_config(const fl_ctx *c, LinkFormat fmt, DslashArgs &a)
@@ -418,12 +420,14 @@ void dslash_config(const fl_ctx *c, LinkFormat fmt, DslashArgs &a)
     }
     a.wsmax = (ws + 3) & ~3;  // 16-byte aligned windows for every site format
     int mode = c->tune_lds[fmt];
-    // built-in (measured at 16^3x32): FP64 windows only; every other format
-    // staged links and no windows (16-bit fields: the packed hop; FP32 and
-    // bf16: 1611 and 1567 us against 1708 and 1651 us with windows, whose
-    // LDS held a CU to one workgroup); a mode that does not fit the LDS
-    // falls back to a smaller one
-    if (mode < 0) mode = fmt == LINK_F64_R18 ? 1 : 4;
+    // built-in (measured at 16^3x32): staged links and no windows (16-bit
+    // fields: the packed hop; FP32 and bf16: 1611 and 1567 us against 1708
+    // and 1651 us with windows, whose LDS held a CU to one workgroup; FP64
+    // with 8 right-hand sides per workgroup: 3483 against 4554 us without
+    // staging, its windows do not fit), except FP64 workgroups of fewer than
+    // 4 right-hand sides (single solves), which keep the windows; a mode
+    // that does not fit the LDS falls back to a smaller one
+    if (mode < 0) mode = (fmt == LINK_F64_R18 && a.B.RT < 4) ? 1 : 4;
     if (mode == 3 && fmt != LINK_Q16_R12) mode = 2;  // the packed integer hop with windows: 16-bit fields only
     // a mode whose staging does not fit falls back: 4 -> 2 -> 1 -> 0 (3 -> 2 -> ...)
     while (mode > 0 && dslash_lds_bytes(fmt, a.B.RT, a.wsmax, mode) > c->max_lds)
