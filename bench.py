@@ -185,6 +185,8 @@ def main():
     ap.add_argument("--lds", type=int, default=-1,
                     help="LDS mode of the hopping kernel (-1: the library default; 3: packed 16-bit hop)")
     ap.add_argument("--rt", type=int, default=0, help="right-hand sides per workgroup (0: the library default)")
+    ap.add_argument("--group", type=int, default=0,
+                    help="right-hand-side blocks that sweep the site blocks together (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the timings of the other workloads (exact loops, uneven TSM batch, gradient)")
@@ -218,8 +220,8 @@ def main():
     solver = fl.SOLVER_CGNR if args.solver == "cgnr" else fl.SOLVER_BICGSTAB
     lp = fl.SolverParams(tol=1e-12, inner_prec=prec, gauge_reals=12, batch=args.batch, solver=solver,
                          delta=args.delta)
-    if args.lds != -1 or args.rt:
-        lat.set_tile(prec=prec, gauge_reals=12, rt=args.rt, group=0, lds=args.lds)
+    if args.lds != -1 or args.rt or args.group:
+        lat.set_tile(prec=prec, gauge_reals=12, rt=args.rt, group=args.group, lds=args.lds)
     nt = dims[3]
     solves_per_step = 12 * nt
 
@@ -479,6 +481,7 @@ def main():
             "batch": args.batch,
             "lds_mode": args.lds,
             "rt": args.rt,
+            "group": args.group,
             "parallelism": "single GPU",
         },
         "roofline": hop_roof(dominant),
