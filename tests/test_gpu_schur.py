@@ -57,8 +57,10 @@ def even_mask(dims):
 
 
 # (6, 4, 4, 6): Vh = 288, a ragged last wave; 3 right-hand sides: a partial
-# workgroup of right-hand sides
-@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (6, 4, 4, 6)])
+# workgroup of right-hand sides; (2, 2, 2, 4): extents of 2, where the
+# forward and backward neighbour of a direction are the same site (both
+# hops add), and a single partial wave
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (6, 4, 4, 6), (2, 2, 2, 4)])
 @pytest.mark.parametrize("prec,reals,lds", CASES)
 @pytest.mark.parametrize("dagger", [False, True])
 def test_schur_operator(F, dims, prec, reals, lds, dagger):
