@@ -146,3 +146,28 @@ def test_statistics_of_converged_loops(F):
     lat.loops_exact_sites(sites, GAMMAS, F.SolverParams(tol=1e-12, inner_prec=3, gauge_reals=12, solver=1))
     st = lat.last_stats()
     assert len(st["iters"]) == 12 * len(sites) and st["converged"].all() and (st["true_resid"] <= 1e-12).all()
+
+
+def test_empty_inputs_do_nothing(F):
+    """Zero right-hand sides, an empty site list and an empty timeslice list
+    are valid calls that launch nothing and return empty results."""
+    dims = (4, 4, 2, 6)
+    lat, _ = make(F, dims, 0.4, 0.12, -1, 61)
+    try:
+        V = S.volume(dims)
+        empty = np.zeros((0, V, 4, 3), complex)
+        print("empty inputs", flush=True)
+        assert lat.apply_D(empty).shape == (0, V, 4, 3)
+        x, info = lat.solve(empty, F.SolverParams(tol=1e-10))
+        assert x.shape == (0, V, 4, 3) and len(info) == 0
+        assert len(lat.last_stats()["iters"]) == 0
+        L = lat.loops_exact_sites([], GAMMAS, F.SolverParams(tol=1e-10))
+        assert L.shape == (len(GAMMAS), 0)
+        L = lat.loops_exact([], GAMMAS, F.SolverParams(tol=1e-10))
+        assert L.shape == (len(GAMMAS), 0, dims[0] * dims[1] * dims[2])
+        # the context still works afterwards
+        b = S.random_spinors(dims, 1, 3)
+        x, info = lat.solve(b, F.SolverParams(tol=1e-10))
+        assert info[0]["converged"]
+    finally:
+        lat.close()
