@@ -187,22 +187,23 @@ def test_autograd_loopfn_matches_oracle(F):
 
 @pytest.mark.parametrize("prec,reals,tol", [(3, 12, 1e-3), (1, 12, 1e-5), (2, 12, 5e-3), (0, 18, 1e-13)],
                          ids=["h16", "f32", "bf16", "f64"])
-def test_schur_operator_16x16x16x32_benchmark_shape(F, prec, reals, tol):
+@pytest.mark.parametrize("dagger", [False, True])
+def test_schur_operator_16x16x16x32_benchmark_shape(F, prec, reals, tol, dagger):
     """The Schur operator at the benchmark's lattice and launch shape (16
     right-hand sides: two blocks of 8 per workgroup, the built-in LDS mode
     of each format: staged links without windows) against the oracle's
-    Dhat on every even site of two of the right-hand sides."""
+    Dhat (and Dhat^+) on every even site of two of the right-hand sides."""
     lat, U, W = lattice(F, "stoch_16x16x16x32")
     try:
         dims = W["dims"]
         psi = S.random_spinors(dims, 16, 707)
         print(f"Schur operator 16^3x32, prec {prec}", flush=True)
-        got = lat.apply_schur(psi, F.SolverParams(inner_prec=prec, gauge_reals=reals))
+        got = lat.apply_schur(psi, F.SolverParams(inner_prec=prec, gauge_reals=reals), dagger=dagger)
         x = np.indices(dims[::-1]).reshape(4, -1)[::-1]
         ev = (x.sum(axis=0) % 2) == 0
         V = S.volume(dims)
         for k in (0, 13):
-            ref = O.apply_Dhat(U, psi[k], dims, W["bc_t"], W["kappa"]).reshape(V, 12)
+            ref = O.apply_Dhat(U, psi[k], dims, W["bc_t"], W["kappa"], dagger=dagger).reshape(V, 12)
             g = got[k].reshape(V, 12)
             assert np.all(g[~ev] == 0)
             err = np.linalg.norm(g[ev] - ref[ev]) / np.linalg.norm(ref[ev])
