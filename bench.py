@@ -12,11 +12,12 @@ arithmetic on 16-bit fixed-point vectors and links, FP64 reliable updates;
 Eq. (loop stochastic) for Gamma = 1, g5, g1..g4.
 
 Prints one JSON line:  value = diluted solves per second (whole job).
-roofline: the dominant kernel of the step, the hopping launch with the
-fused epilogue that ends each CGNR iteration (events around every launch on
-the library's stream; algorithmic bytes = 8 links per site + its input,
-its two own-site operands and its output per site and right-hand side);
-roofline_first_hop: the iteration's first hop, H_oe (input + output).  cpu_baseline: the FP64 oracle solving one of the
+roofline: the dominant kernel of the step, the one of the iteration's
+timed kernels with the largest summed time (events around every launch on
+the library's stream): the first hop H_oe (algorithmic bytes = 8 links per
+site + input + output per site and right-hand side), the hop with the fused
+epilogue that ends each CGNR iteration (+ its two own-site operands), or
+the vector update of x and p (5 fields); roofline_by_kernel: all three.  cpu_baseline: the FP64 oracle solving one of the
 same diluted sources on the host cores.
 """
 import argparse
@@ -46,9 +47,10 @@ def traffic_profile(prec):
     return os.path.join(ROOT, "profiles", f"hopping_{prec}r12_stoch_16x16x16x32.md")
 
 
-# the two timed hopping launches: library profiling slot and the vector
-# fields each reads or writes once per site and right-hand side (CGNR)
-HOPS = {"first_hop": (0, 2), "end_hop": (1, 4)}
+# the timed kernels of the iteration: library profiling slot, the vector
+# fields each reads or writes once per site and right-hand side (CGNR), and
+# whether it reads the links (a hop)
+HOPS = {"first_hop": (0, 2, True), "end_hop": (1, 4, True), "vector_update": (2, 5, False)}
 
 
 def kernel_source_hash():
@@ -240,8 +242,8 @@ def main():
         t0 = time.perf_counter()
         step(1000 + k)
         log(f"[bench] warmup step {k}: {time.perf_counter() - t0:.2f}s")
-    lat.profile_enable(fl.PROF_DSLASH, True)
-    lat.profile_enable(fl.PROF_DSLASH_END, True)
+    for slot, _, _ in HOPS.values():
+        lat.profile_enable(slot, True)
     torch.cuda.synchronize()
     w_steps = time.monotonic_ns()
     t0 = time.perf_counter()
@@ -273,20 +275,23 @@ def main():
             fl.append_jsonl(args.metrics_jsonl, fl.stats_records(st, step=k, workload="stochastic_16x16x16x32",
                                                                  prec=args.prec, solver=args.solver))
     profs = {}
-    for name, (slot, _) in HOPS.items():
+    for name, (slot, _, _) in HOPS.items():
         pr = lat.profile_read(slot)
         lat.profile_enable(slot, False)
         pr["avg_us"] = pr["ms"] * 1e3 / max(1, pr["launches"])
         pr["achieved"] = pr["bytes"] / (pr["ms"] * 1e-3) / 1e9 if pr["ms"] > 0 else 0.0
         profs[name] = pr
-    # the roofline is reported for the kernel that takes the most time
+    # the roofline is reported for the kernel of the iteration that takes
+    # the most time (the two epilogue-free hops and the end hop, the vector
+    # update; nothing else comes near them)
     dominant = max(profs, key=lambda h: profs[h]["ms"])
     prof = profs["first_hop"]
     achieved, avg_us = prof["achieved"], prof["avg_us"]
     value = solves_per_step * args.steps / T
     log(f"[bench] {value:.1f} solves/s; hopping kernel {prof['launches']} launches, avg {avg_us:.1f} us, "
         f"{achieved:.0f} GB/s; end hop avg {profs['end_hop']['avg_us']:.1f} us, "
-        f"{profs['end_hop']['achieved']:.0f} GB/s; dominant: {dominant}")
+        f"{profs['end_hop']['achieved']:.0f} GB/s; vector update avg {profs['vector_update']['avg_us']:.1f} us, "
+        f"{profs['vector_update']['achieved']:.0f} GB/s; dominant: {dominant}")
 
     # disconnected two-point function (Eq. all_dis_corr) from the timed steps
     # loops: two independent noise vectors, 33 momenta with |n|^2 <= 3, all
@@ -333,7 +338,10 @@ def main():
                                              "achieved_GBs": round(achieved, 1)},
                           "end_hop_kernel": {"launches": profs["end_hop"]["launches"],
                                              "avg_launch_us": round(profs["end_hop"]["avg_us"], 2),
-                                             "achieved_GBs": round(profs["end_hop"]["achieved"], 1)}}),
+                                             "achieved_GBs": round(profs["end_hop"]["achieved"], 1)},
+                          "vector_update_kernel": {"launches": profs["vector_update"]["launches"],
+                                                   "avg_launch_us": round(profs["vector_update"]["avg_us"], 2),
+                                                   "achieved_GBs": round(profs["vector_update"]["achieved"], 1)}}),
               flush=True)
         return
     # the other workloads of the path, timed once each outside the timed region:
@@ -434,24 +442,30 @@ def main():
         # site x right-hand-side pairs per launch from the algorithmic bytes
         # (8 links per site once, the hop's fields once per pair); the FP32
         # rate counts the hopping term's flops only
-        pr, fields = profs[name], HOPS[name][1]
-        if name == "end_hop" and args.solver != "cgnr":
-            fields = 3  # BiCGStab: t = Dhat s reads s at the site
+        pr, fields, hop = profs[name], HOPS[name][1], HOPS[name][2]
+        if args.solver != "cgnr":
+            fields = {"first_hop": 2, "end_hop": 3, "vector_update": 7}[name]  # BiCGStab
         bpl = pr["bytes"] / max(1, pr["launches"])
-        pairs = (bpl - 8 * LINK_BYTES[args.prec] * Vh) / (fields * SITE_BYTES[args.prec])
-        tflops = FLOP_PER_SITE * pairs / (pr["avg_us"] * 1e-6) / 1e12 if pr["avg_us"] > 0 else 0.0
         label = {"first_hop": "hopping term H_oe of Dhat p (no epilogue)",
                  "end_hop": "hopping term H_eo of Dhat^+ q with the fused update z -= alpha (q + c H q') "
                             "and |z|^2 (reads q and z at the site)" if args.solver == "cgnr" else
-                            "hopping term H_eo of Dhat s with <t, s> and |t|^2 (reads s at the site)"}[name]
-        # every storage format's hopping kernel is limited by the memory
-        # system; the FP32 rate is reported beside it
-        return {"kernel": f"{label}, {args.prec} storage, 12-real links, iteration launches",
-                "bound": "hbm", "achieved": round(pr["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(pr["achieved"] / HBM_PEAK_GBS, 4), "fp32_TFLOPs": round(tflops, 2),
-                "fp32_frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": profiled_traffic(args.prec, name),
-                "avg_launch_us": round(pr["avg_us"], 2), "launches": pr["launches"],
-                "share_of_step": round(pr["ms"] * 1e-3 / T, 4), "algorithmic_bytes_per_launch": round(bpl)}
+                            "hopping term H_eo of Dhat s with <t, s> and |t|^2 (reads s at the site)",
+                 "vector_update": "vector update x += alpha p, p = z + beta p" if args.solver == "cgnr" else
+                                  "vector update x += alpha p + omega s, r = s - omega t"}[name]
+        # every kernel of the iteration is limited by the memory system; the
+        # FP32 rate of the hopping term is reported beside a hop's figure
+        out = {"kernel": f"{label}, {args.prec} storage" + (", 12-real links" if hop else "") +
+                         ", iteration launches",
+               "bound": "hbm", "achieved": round(pr["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(pr["achieved"] / HBM_PEAK_GBS, 4)}
+        if hop:
+            pairs = (bpl - 8 * LINK_BYTES[args.prec] * Vh) / (fields * SITE_BYTES[args.prec])
+            tflops = FLOP_PER_SITE * pairs / (pr["avg_us"] * 1e-6) / 1e12 if pr["avg_us"] > 0 else 0.0
+            out.update({"fp32_TFLOPs": round(tflops, 2), "fp32_frac": round(tflops / FP32_PEAK_TFLOPS, 4)})
+        out.update({"traffic": profiled_traffic(args.prec, name), "avg_launch_us": round(pr["avg_us"], 2),
+                    "launches": pr["launches"], "share_of_step": round(pr["ms"] * 1e-3 / T, 4),
+                    "algorithmic_bytes_per_launch": round(bpl)})
+        return out
 
     out = {
         "metric": METRIC,
@@ -485,7 +499,7 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": hop_roof(dominant),
-        "roofline_first_hop": hop_roof("first_hop"),
+        "roofline_by_kernel": {name: hop_roof(name) for name in HOPS},
         "iteration_roofline": iteration_roofline(args.solver, args.prec, Vh, float(iters.sum()) / args.steps,
                                                  ITER_HOPS * float(iters.max()), T / args.steps),
         "cpu_baseline": cpu,

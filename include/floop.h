@@ -290,8 +290,11 @@ fl_status fl_loops_grad(fl_ctx *ctx, const int *t0, int nt, const int *gammas, i
  *     operator work of an iteration: for CGNR the second hop of Dhat^+ q
  *     with z -= alpha (q + c H q') and |z|^2 (reads q and z at the site), for
  *     truncated CGNR the second hop of Dhat^+ r with |z|^2, for BiCGStab
- *     the second hop of Dhat s with <t, s> and |t|^2 (reads s at the site). */
-enum { FL_PROF_DSLASH = 0, FL_PROF_DSLASH_END = 1, FL_PROF_NKERNELS = 4 };
+ *     the second hop of Dhat s with <t, s> and |t|^2 (reads s at the site).
+ *   FL_PROF_BLAS_UPDATE: the vector update of every iteration: for CGNR
+ *     x += alpha p and p = z + beta p (5 field passes), for BiCGStab
+ *     x += alpha p + omega s and r = s - omega t (7 field passes). */
+enum { FL_PROF_DSLASH = 0, FL_PROF_DSLASH_END = 1, FL_PROF_BLAS_UPDATE = 2, FL_PROF_NKERNELS = 4 };
 fl_status fl_profile_enable(fl_ctx *ctx, int kernel, int enable);
 fl_status fl_profile_read(fl_ctx *ctx, int kernel, double *ms, long long *launches,
                           double *bytes);

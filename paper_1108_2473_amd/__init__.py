@@ -25,7 +25,9 @@ PREC_F64, PREC_F32, PREC_BF16, PREC_H16 = 0, 1, 2, 3
 SOLVER_BICGSTAB, SOLVER_CGNR = 0, 1
 NOISE_Z4, NOISE_CZ2, NOISE_Z2 = 0, 1, 2
 DIL_TIME, DIL_SPIN, DIL_COLOUR, DIL_EVENODD, DIL_CUBIC = 1, 2, 4, 8, 16
-PROF_DSLASH, PROF_DSLASH_END = 0, 1  # the first hop of an iteration; the hop with the fused epilogue ending it
+# profiling slots: the first hop of an iteration; the hop with the fused
+# epilogue ending it; the iteration's vector update (x and p)
+PROF_DSLASH, PROF_DSLASH_END, PROF_BLAS_UPDATE = 0, 1, 2
 GAMMA_1, GAMMA_5 = 0, 15
 GAMMAS_PAPER = [0, 15, 1, 2, 4, 8]  # 1, g5, g1, g2, g3, g4
 

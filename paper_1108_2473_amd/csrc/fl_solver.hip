@@ -99,7 +99,8 @@ struct Solver {
         if (pslot >= 0) prof_end(c0, pslot, 0.0);
     }
 
-    void blas(VecFormat f, int op, std::initializer_list<const MF *> fields, int flag, int slot0, const int *msk)
+    void blas(VecFormat f, int op, std::initializer_list<const MF *> fields, int flag, int slot0, const int *msk,
+              int pslot = -1)
     {
         BlasArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -117,7 +118,9 @@ struct Solver {
             for (int l = 0; l < B.nlat; ++l) a.f[k][l] = f->p[l];
             ++k;
         }
+        if (pslot >= 0) prof_begin(c0, pslot);
         launch_blas(f, a, st);
+        if (pslot >= 0) prof_end(c0, pslot, 0.0);
     }
 
     void scal(int step, const int *msk)
@@ -155,7 +158,7 @@ struct Solver {
         blas(lf, OP_BICG_S, {&R, &V, &S}, 0, 0, active);          // s = r - alpha v
         schur_lo(S, T, EPI_DOTX_NORM, nullptr, 0, false, -1, FL_PROF_DSLASH_END);  // t = Dhat s, <t, s>, |t|^2
         scal(SC_OMEGA, nullptr);
-        blas(lf, OP_BICG_XR, {&XL, &P, &S, &T, &R, &R0}, 0, 0, active);
+        blas(lf, OP_BICG_XR, {&XL, &P, &S, &T, &R, &R0}, 0, 0, active, FL_PROF_BLAS_UPDATE);
         scal(SC_BETA, nullptr);
         blas(lf, OP_BICG_P, {&P, &R, &V}, 0, 0, active);          // p = r + beta (p - omega v)
     }
@@ -189,7 +192,7 @@ struct Solver {
         }
         scal(SC_CG_BETA, nullptr);
         // x += alpha p (also for a system that stopped in SC_CG_BETA), then p = z + beta p
-        blas(lf, OP_CG_PX, {&P, &S, &XL}, 0, 0, active);
+        blas(lf, OP_CG_PX, {&P, &S, &XL}, 0, 0, active, FL_PROF_BLAS_UPDATE);
     }
 
     // FP64 residual of the masked systems: rh = bh - Dhat xh (|rh|^2 -> slot 2),
@@ -432,15 +435,20 @@ fl_status Solver::run(std::vector<SysResult> &res)
             if (k >= B.lat[q].sys0) l = q;
         return l;
     };
-    // vector fields each profiled hop reads or writes once per site and
+    // vector fields each profiled kernel reads or writes once per site and
     // system: the first hop its input and output; the hop that ends the
     // iteration also its own-site operands (CGNR: q and z; truncated CGNR
-    // and BiCGStab: r resp. s)
-    const int prof_fields[2] = {2, (solver == FL_SOLVER_CGNR && !trunc) ? 4 : 3};
-    size_t prof_mark[2] = {c0->prof[FL_PROF_DSLASH].ev.size(), c0->prof[FL_PROF_DSLASH_END].ev.size()};
+    // and BiCGStab: r resp. s); the vector update x and p (CGNR: p, z and x
+    // read, x and p written; BiCGStab: x, p, s, t, r0 read, x and r written).
+    // Links are counted for the hops only.
+    const int prof_slot[3] = {FL_PROF_DSLASH, FL_PROF_DSLASH_END, FL_PROF_BLAS_UPDATE};
+    const int prof_fields[3] = {2, (solver == FL_SOLVER_CGNR && !trunc) ? 4 : 3,
+                                solver == FL_SOLVER_CGNR ? 5 : 7};
+    size_t prof_mark[3];
+    for (int k = 0; k < 3; ++k) prof_mark[k] = c0->prof[prof_slot[k]].ev.size();
     auto account_prof = [&]() {
-        for (int k = 0; k < 2; ++k) {
-            ProfSlot &ps = c0->prof[k == 0 ? FL_PROF_DSLASH : FL_PROF_DSLASH_END];
+        for (int k = 0; k < 3; ++k) {
+            ProfSlot &ps = c0->prof[prof_slot[k]];
             if (!ps.on) continue;
             size_t nnew = ps.ev.size() - prof_mark[k];
             prof_mark[k] = ps.ev.size();
@@ -451,7 +459,7 @@ fl_status Solver::run(std::vector<SysResult> &res)
             double bytes = 0;
             for (int l = 0; l < B.nlat; ++l) {
                 const double lb = (double)link_bytes(fmt);
-                bytes += 8.0 * lb * B.lat[l].Vh +
+                bytes += (k < 2 ? 8.0 * lb * B.lat[l].Vh : 0.0) +
                          prof_fields[k] * lo_bytes_per_site_rhs() * B.lat[l].Vh * active_count[l];
             }
             ps.bytes += bytes * nnew;

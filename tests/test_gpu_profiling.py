@@ -1,8 +1,9 @@
-"""Live kernel timing of the two hops that the benchmark reports
-(fl_profile_enable / fl_profile_read): for a CGNR solve both slots see one
-launch per iteration chunk step, the end hop's algorithmic bytes count two
-more fields per site and right-hand side than H_oe's, and both times are
-positive.  BiCGStab fills the same slots."""
+"""Live kernel timing of the three iteration kernels that the benchmark
+reports (fl_profile_enable / fl_profile_read): for a CGNR solve every slot
+sees one launch per iteration, the end hop's algorithmic bytes count two
+more fields per site and right-hand side than H_oe's, the vector update's
+five fields and no links, and all times are positive.  BiCGStab fills the
+same slots (its end hop three fields, its update seven)."""
 import numpy as np
 import pytest
 
@@ -22,11 +23,12 @@ def test_first_and_end_hop_slots(solver, fields_end):
         b = S.random_spinors(dims, 4, 5)
         prm = fl.SolverParams(tol=1e-10, solver=solver, inner_prec=fl.PREC_H16)
         print(f"profiling slots, solver {solver}", flush=True)
-        for k in (fl.PROF_DSLASH, fl.PROF_DSLASH_END):
+        slots = (fl.PROF_DSLASH, fl.PROF_DSLASH_END, fl.PROF_BLAS_UPDATE)
+        for k in slots:
             lat.profile_enable(k, True)
         x, info = lat.solve(b, prm)
-        first, end = lat.profile_read(fl.PROF_DSLASH), lat.profile_read(fl.PROF_DSLASH_END)
-        for k in (fl.PROF_DSLASH, fl.PROF_DSLASH_END):
+        first, end, upd = (lat.profile_read(k) for k in slots)
+        for k in slots:
             lat.profile_enable(k, False)
         assert all(s["converged"] for s in info)
         iters = max(s["iters"] for s in info)
@@ -38,5 +40,9 @@ def test_first_and_end_hop_slots(solver, fields_end):
         per_field_first = (first["bytes"] - links) / 2
         per_field_end = (end["bytes"] - links) / fields_end
         assert per_field_first > 0 and abs(per_field_end - per_field_first) <= 1e-9 * per_field_first
+        # the vector update: one launch per iteration, no links, 5 (CGNR) or 7 (BiCGStab) fields
+        assert upd["launches"] == first["launches"] and upd["ms"] > 0
+        per_field_upd = upd["bytes"] / (5 if solver == 1 else 7)
+        assert abs(per_field_upd - per_field_first) <= 1e-9 * per_field_first
     finally:
         lat.close()
