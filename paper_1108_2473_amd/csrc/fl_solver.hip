@@ -63,6 +63,7 @@ struct Solver {
     double *partial = nullptr;
     SysState *dst = nullptr;
     int stamp = 0;  // CGNR iteration stamp
+    int flip = 0;   // sweep direction of the next launch (BatchGeom::rev)
     int *active = nullptr, *mask = nullptr;
     PinArr<SysState> hst;
     PinArr<int> hact, hmask, hm2;  // hm2: the masks of restarts and CGNR replacements
@@ -93,6 +94,8 @@ struct Solver {
             a.ca[l] = ca;
             a.cb[l] = cbv ? cbv[l] : 1.0;
         }
+        a.B.rev = flip;
+        flip ^= 1;
         dslash_config(c0, f, a);
         if (pslot >= 0) prof_begin(c0, pslot);
         launch_dslash(f, a, dag, epi, st);
@@ -118,6 +121,8 @@ struct Solver {
             for (int l = 0; l < B.nlat; ++l) a.f[k][l] = f->p[l];
             ++k;
         }
+        a.B.rev = flip;
+        flip ^= 1;
         if (pslot >= 0) prof_begin(c0, pslot);
         launch_blas(f, a, st);
         if (pslot >= 0) prof_end(c0, pslot, 0.0);
