@@ -101,6 +101,19 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
         SpinorFmt<H16>::load(spinor_buf<H16>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, y16);
 #pragma unroll
         for (int k = 0; k < 12; ++k) out[k] = out[k] - cx<double>{(double)y16[k].re, (double)y16[k].im};
+        if constexpr ((EPI & EPI_ACCX) != 0) {
+            // the solution moves by the same decoded values at this site:
+            // w += y, then y = 0 (the accumulation of a reliable update)
+            cx<double> h[12];
+            SpinorFmt<double>::load(spinor_buf<double>(a.w[T.lat], g.Vh, rhs), g.Vh, T.site, h);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) h[k] = h[k] + cx<double>{(double)y16[k].re, (double)y16[k].im};
+            store_result<double>(spinor_buf<double>(a.w[T.lat], g.Vh, rhs), g.Vh, T.site, h);
+            cx<float> z[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) z[k] = cx<float>{0.0f, 0.0f};
+            store_result<H16>(spinor_buf<H16>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, z);
+        }
     }
     if constexpr (std::is_same<S, H16>::value && !(EPI & (EPI_DOTX_NORM | EPI_DOTY))) {
         // 16-bit result without dot products: stored as words, its norm
@@ -468,6 +481,12 @@ void dispatch_epi(const DslashArgs &a, int epi, dim3 grid, dim3 block, hipStream
         else
             launch_unsupported("hopping epilogue: 16-bit subtraction needs FP64 fields");
         break;
+    case EPI_XPAY | EPI_NORM | EPI_SUBY16 | EPI_ACCX:
+        if constexpr (std::is_same<S, double>::value)
+            launch_one<S, LK, DAG, EPI_XPAY | EPI_NORM | EPI_SUBY16 | EPI_ACCX>(a, grid, block, s);
+        else
+            launch_unsupported("hopping epilogue: 16-bit subtraction needs FP64 fields");
+        break;
     default: launch_unsupported("hopping epilogue"); break;
     }
 }
@@ -499,7 +518,8 @@ bool dslash_epi_supported(int epi)
 {
     return epi == EPI_PLAIN || epi == EPI_XPAY || epi == (EPI_XPAY | EPI_NORM) ||
            epi == (EPI_XPAY | EPI_DOTY) || epi == (EPI_XPAY | EPI_DOTX_NORM) || epi == EPI_NORM ||
-           epi == (EPI_XPAY | EPI_NORM | EPI_SUBY16) || epi == (EPI_XPAY | EPI_NORM | EPI_CGZ);
+           epi == (EPI_XPAY | EPI_NORM | EPI_SUBY16) || epi == (EPI_XPAY | EPI_NORM | EPI_CGZ) ||
+           epi == (EPI_XPAY | EPI_NORM | EPI_SUBY16 | EPI_ACCX);
 }
 
 void launch_dslash_h16_wide(const DslashArgs &a, bool dag, hipStream_t s)

@@ -39,7 +39,8 @@ enum {
     EPI_DOTX_NORM = 4,  // slots slot0, slot0+1: <out, x>; slot0+2: |out|^2
     EPI_NORM = 8,       // slot0+2: |out|^2
     EPI_SUBY16 = 16,    // FP64 fields only: out -= y, y a 16-bit field (its decoded values)
-    EPI_CGZ = 32        // with EPI_XPAY: out = y - alpha (ca x + cb H in), alpha = st[sys].alpha[0]
+    EPI_CGZ = 32,       // with EPI_XPAY: out = y - alpha (ca x + cb H in), alpha = st[sys].alpha[0]
+    EPI_ACCX = 64       // with EPI_SUBY16: also w += y (FP64 += the decoded 16-bit values), then y = 0
                         // (CGNR: z -= alpha Dhat^+ q, y = z updated in place)
 };
 
@@ -62,6 +63,7 @@ struct DslashArgs {
                 // 2: also the workgroup's links staged in LDS once
     int wsmax;  // LDS window length in sites (64 + 2 * max Lx/2), set by the launcher
     const SysState *st;  // per-system scalars (EPI_CGZ)
+    void *w[FL_MAXLAT];  // the FP64 field of EPI_ACCX
 };
 
 bool dslash_epi_supported(int epi);

@@ -74,7 +74,8 @@ struct Solver {
     double lo_bytes_per_site_rhs() const { return (double)vec_site_bytes(vf); }
 
     void dslash(LinkFormat f, bool lo, int par, const MF &in, const MF &out, const MF *x, const MF *y,
-                double ca, const double *cbv, int epi, int slot0, const int *msk, bool dag, int pslot)
+                double ca, const double *cbv, int epi, int slot0, const int *msk, bool dag, int pslot,
+                const MF *w = nullptr)
     {
         DslashArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -90,6 +91,7 @@ struct Solver {
             a.out[l] = out.p[l];
             a.x[l] = x ? x->p[l] : nullptr;
             a.y[l] = y ? y->p[l] : nullptr;
+            a.w[l] = w ? w->p[l] : nullptr;
             a.gauge[l] = lo ? gauge_lo[l] : gauge_hi[l];
             a.ca[l] = ca;
             a.cb[l] = cbv ? cbv[l] : 1.0;
@@ -227,9 +229,9 @@ struct Solver {
                 a.cb[l] = 1.0;
             }
             launch_dslash_h16_wide(a, false, st);                      // t = H_oe xl
-            dslash(LINK_F64_R18, false, 0, T64, RH, &RH, &XL, 1.0, pos_k2, EPI_XPAY | EPI_NORM | EPI_SUBY16, 0, msk,
-                   false, -1);                                         // rh += k^2 H_eo t - xl
-            blas(vf, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                // xh += xl, xl = 0
+            // rh += k^2 H_eo t - xl, and in the same epilogue xh += xl, xl = 0
+            dslash(LINK_F64_R18, false, 0, T64, RH, &RH, &XL, 1.0, pos_k2,
+                   EPI_XPAY | EPI_NORM | EPI_SUBY16 | EPI_ACCX, 0, msk, false, -1, &XH);
         } else {
             blas(vf, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                // xh += xl, xl = 0
             blas(VEC_F64, OP_SUB_HI, {&RH, &BH, &XH}, 0, 0, msk);      // rh = bh - xh
