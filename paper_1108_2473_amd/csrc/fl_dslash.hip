@@ -96,23 +96,26 @@ __device__ __forceinline__ void epilogue(const DslashArgs &a, const TileInfo &T,
 #pragma unroll
         for (int k = 0; k < 12; ++k) out[k] = cx<R>{fma(-al, out[k].re, yv[k].re), fma(-al, out[k].im, yv[k].im)};
     }
-    if constexpr ((EPI & EPI_SUBY16) != 0 && std::is_same<S, double>::value) {
-        cx<float> y16[12];
-        SpinorFmt<H16>::load(spinor_buf<H16>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, y16);
+    if constexpr ((EPI & (EPI_SUBY16 | EPI_SUBY32)) != 0 && std::is_same<S, double>::value) {
+        // y in the iteration's format: its values (16-bit: the decoded ones)
+        // widen to FP64 exactly
+        typedef typename std::conditional<(EPI & EPI_SUBY16) != 0, H16, float>::type Y;
+        cx<float> yl[12];
+        SpinorFmt<Y>::load(spinor_buf<Y>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, yl);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) out[k] = out[k] - cx<double>{(double)y16[k].re, (double)y16[k].im};
+        for (int k = 0; k < 12; ++k) out[k] = out[k] - cx<double>{(double)yl[k].re, (double)yl[k].im};
         if constexpr ((EPI & EPI_ACCX) != 0) {
-            // the solution moves by the same decoded values at this site:
-            // w += y, then y = 0 (the accumulation of a reliable update)
+            // the solution moves by the same values at this site: w += y,
+            // then y = 0 (the accumulation of a reliable update)
             cx<double> h[12];
             SpinorFmt<double>::load(spinor_buf<double>(a.w[T.lat], g.Vh, rhs), g.Vh, T.site, h);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) h[k] = h[k] + cx<double>{(double)y16[k].re, (double)y16[k].im};
+            for (int k = 0; k < 12; ++k) h[k] = h[k] + cx<double>{(double)yl[k].re, (double)yl[k].im};
             store_result<double>(spinor_buf<double>(a.w[T.lat], g.Vh, rhs), g.Vh, T.site, h);
             cx<float> z[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) z[k] = cx<float>{0.0f, 0.0f};
-            store_result<H16>(spinor_buf<H16>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, z);
+            store_result<Y>(spinor_buf<Y>(a.y[T.lat], g.Vh, rhs), g.Vh, T.site, z);
         }
     }
     if constexpr (std::is_same<S, H16>::value && !(EPI & (EPI_DOTX_NORM | EPI_DOTY))) {
@@ -183,10 +186,11 @@ __global__ __launch_bounds__(sizeof(typename SpinorFmt<S>::R) == 8 ? 512 : 1024)
     reduce_partials<EPI>(a, T, q0, q1, q2);
 }
 
-// a 16-bit field read into FP64 arithmetic: the decoded values (the stored
-// integers times the site scale, rounded to FP32 exactly as every other
-// reader of the field decodes them) widen to FP64 without rounding
-struct H16WideSrc {
+// a 16-bit or FP32 field read into FP64 arithmetic: its values (16-bit: the
+// stored integers times the site scale, rounded to FP32 exactly as every
+// other reader of the field decodes them) widen to FP64 without rounding
+template <typename Y>
+struct WideSrc {
     static constexpr bool PACKED_I16 = false;
     static constexpr double LINK_UNIT = LinkF64R18::UNIT;
     Buf in, gauge;
@@ -195,7 +199,7 @@ struct H16WideSrc {
     __device__ __forceinline__ double spinor(int i, cx<double> s[12]) const
     {
         cx<float> f[12];
-        SpinorFmt<H16>::load(in, Vh, i, f);
+        SpinorFmt<Y>::load(in, Vh, i, f);
 #pragma unroll
         for (int k = 0; k < 12; ++k) s[k] = cx<double>{(double)f[k].re, (double)f[k].im};
         return 1.0;
@@ -206,8 +210,8 @@ struct H16WideSrc {
     }
 };
 
-template <bool DAG>
-__global__ __launch_bounds__(512) void k_dslash_h16_wide(DslashArgs a)
+template <typename Y, bool DAG>
+__global__ __launch_bounds__(512) void k_dslash_wide(DslashArgs a)
 {
     typedef LinkF64R18 LK;
     TileInfo T = tile_info(a.B);
@@ -218,8 +222,8 @@ __global__ __launch_bounds__(512) void k_dslash_h16_wide(DslashArgs a)
     double q0 = 0, q1 = 0, q2 = 0;
     if (T.valid_site) {
         Coord c = cb_coords(g, a.par, T.site);
-        H16WideSrc src;
-        src.in = spinor_buf<H16>(a.in[T.lat], g.Vh, rhs);
+        WideSrc<Y> src;
+        src.in = spinor_buf<Y>(a.in[T.lat], g.Vh, rhs);
         src.gauge = make_buf(a.gauge[T.lat], (unsigned)(8u * LK::NC * LK::ESZ * (unsigned)g.Vh));
         src.Vh = g.Vh;
         cx<double> acc[12];
@@ -487,6 +491,12 @@ void dispatch_epi(const DslashArgs &a, int epi, dim3 grid, dim3 block, hipStream
         else
             launch_unsupported("hopping epilogue: 16-bit subtraction needs FP64 fields");
         break;
+    case EPI_XPAY | EPI_NORM | EPI_SUBY32 | EPI_ACCX:
+        if constexpr (std::is_same<S, double>::value)
+            launch_one<S, LK, DAG, EPI_XPAY | EPI_NORM | EPI_SUBY32 | EPI_ACCX>(a, grid, block, s);
+        else
+            launch_unsupported("hopping epilogue: FP32 subtraction needs FP64 fields");
+        break;
     default: launch_unsupported("hopping epilogue"); break;
     }
 }
@@ -519,17 +529,26 @@ bool dslash_epi_supported(int epi)
     return epi == EPI_PLAIN || epi == EPI_XPAY || epi == (EPI_XPAY | EPI_NORM) ||
            epi == (EPI_XPAY | EPI_DOTY) || epi == (EPI_XPAY | EPI_DOTX_NORM) || epi == EPI_NORM ||
            epi == (EPI_XPAY | EPI_NORM | EPI_SUBY16) || epi == (EPI_XPAY | EPI_NORM | EPI_CGZ) ||
-           epi == (EPI_XPAY | EPI_NORM | EPI_SUBY16 | EPI_ACCX);
+           epi == (EPI_XPAY | EPI_NORM | EPI_SUBY16 | EPI_ACCX) || epi == (EPI_XPAY | EPI_NORM | EPI_SUBY32 | EPI_ACCX);
 }
 
-void launch_dslash_h16_wide(const DslashArgs &a, bool dag, hipStream_t s)
+void launch_dslash_wide(const DslashArgs &a, VecFormat yf, bool dag, hipStream_t s)
 {
     if (a.B.ntiles == 0) return;
     dim3 grid(a.B.ntiles), block(FL_WAVE * a.B.RT);
-    if (dag)
-        hipLaunchKernelGGL((k_dslash_h16_wide<true>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((k_dslash_h16_wide<false>), grid, block, 0, s, a);
+    if (yf == VEC_H16) {
+        if (dag)
+            hipLaunchKernelGGL((k_dslash_wide<H16, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_dslash_wide<H16, false>), grid, block, 0, s, a);
+    } else if (yf == VEC_F32) {
+        if (dag)
+            hipLaunchKernelGGL((k_dslash_wide<float, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_dslash_wide<float, false>), grid, block, 0, s, a);
+    } else {
+        launch_unsupported("widening hop: input format");
+    }
 }
 
 void launch_dslash(LinkFormat fmt, const DslashArgs &a, bool dag, int epi, hipStream_t s)

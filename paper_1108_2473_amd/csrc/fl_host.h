@@ -40,8 +40,9 @@ enum {
     EPI_NORM = 8,       // slot0+2: |out|^2
     EPI_SUBY16 = 16,    // FP64 fields only: out -= y, y a 16-bit field (its decoded values)
     EPI_CGZ = 32,       // with EPI_XPAY: out = y - alpha (ca x + cb H in), alpha = st[sys].alpha[0]
-    EPI_ACCX = 64       // with EPI_SUBY16: also w += y (FP64 += the decoded 16-bit values), then y = 0
+    EPI_ACCX = 64,      // with EPI_SUBY16 or EPI_SUBY32: also w += y (FP64 += the values of y), then y = 0
                         // (CGNR: z -= alpha Dhat^+ q, y = z updated in place)
+    EPI_SUBY32 = 128    // FP64 fields only: out -= y, y an FP32 field
 };
 
 struct SysState;
@@ -77,7 +78,9 @@ size_t dslash_lds_bytes(LinkFormat fmt, int RT, int wsmax, int lds);
 void launch_dslash(LinkFormat fmt, const DslashArgs &a, bool dag, int epi, hipStream_t s);
 // out = H in in FP64 arithmetic with FP64 links on a 16-bit input field (its
 // decoded values, widened exactly), FP64 output; RT <= 8
-void launch_dslash_h16_wide(const DslashArgs &a, bool dag, hipStream_t s);
+// hop of a 16-bit or FP32 field (yf: VEC_H16 or VEC_F32) with FP64 links
+// into an FP64 field, in FP64 arithmetic, no epilogue
+void launch_dslash_wide(const DslashArgs &a, VecFormat yf, bool dag, hipStream_t s);
 
 // per-system Krylov state kept on the device
 struct SysState {

@@ -205,15 +205,24 @@ struct Solver {
     // FP64 residual of the masked systems: rh = bh - Dhat xh (|rh|^2 -> slot 2),
     // then the iteration residual r = lo(rh) with <r0, r>, |r|^2 (slots 3..5);
     // init = 1 also restarts the recurrence (r0 = p = r, xl = 0).
-    // With 16-bit iteration vectors rh = bh - Dhat xh holds between
+    // With FP32 or 16-bit iteration vectors rh = bh - Dhat xh holds between
     // replacements, and the update is rh -= Dhat xl (FP64 arithmetic on the
-    // decoded values of xl, the same values that xh += xl adds), which reads
-    // xl instead of xh in the first hop and needs no rh = bh - xh pass; the
-    // rounding this accumulates stays at the FP64 level of |b| (the stopping
-    // rule on the full operator is checked separately by the callers)
+    // values of xl, the same values that xh += xl adds), which reads xl
+    // instead of xh in the first hop and needs no rh = bh - xh pass.  Its
+    // rounding is relative to |Dhat xl|, about the residual of the previous
+    // replacement, where rh = bh - Dhat xh computed afresh carries an error of
+    // the FP64 rounding of |b| whatever the residual: far below tol, but at
+    // |r| ~ 1e-8 |b| a perturbation of 1e-8 |r| in a direction unrelated to
+    // the Krylov space, which BiCGStab's <r0, r> recurrences amplify.  The
+    // carried residual keeps the rounding of every update, relative to the
+    // size of each xl: bf16 links, whose operator error (~4e-3) lets
+    // BiCGStab's iterate swing far between replacements, and restarts after a
+    // breakdown recompute rh from xh instead (the stopping rule on the full
+    // operator is checked separately by the callers)
     void replace_residual(const int *msk, int init)
     {
-        if (vf == VEC_H16) {
+        const bool carry = vf != VEC_F64 && fmt != LINK_BF16_R12 && !init;
+        if (carry) {
             DslashArgs a;
             std::memset(&a, 0, sizeof(a));
             a.B = B64;
@@ -228,10 +237,11 @@ struct Solver {
                 a.ca[l] = 1.0;
                 a.cb[l] = 1.0;
             }
-            launch_dslash_h16_wide(a, false, st);                      // t = H_oe xl
+            launch_dslash_wide(a, vf, false, st);                      // t = H_oe xl
             // rh += k^2 H_eo t - xl, and in the same epilogue xh += xl, xl = 0
             dslash(LINK_F64_R18, false, 0, T64, RH, &RH, &XL, 1.0, pos_k2,
-                   EPI_XPAY | EPI_NORM | EPI_SUBY16 | EPI_ACCX, 0, msk, false, -1, &XH);
+                   EPI_XPAY | EPI_NORM | (vf == VEC_H16 ? EPI_SUBY16 : EPI_SUBY32) | EPI_ACCX, 0, msk, false, -1,
+                   &XH);
         } else {
             blas(vf, OP_ACC_HI, {&XH, &XL}, 1, 0, msk);                // xh += xl, xl = 0
             blas(VEC_F64, OP_SUB_HI, {&RH, &BH, &XH}, 0, 0, msk);      // rh = bh - xh
