@@ -70,6 +70,26 @@ def _cplx(a):
     return np.ascontiguousarray(a, dtype=np.complex128)
 
 
+def _gauge(U, dims):
+    """U as complex128 after checking that it holds 4 x V links (the C side
+    trusts the sizes it is given)."""
+    U = _cplx(U)
+    if U.size != 4 * int(np.prod(dims)) * 9:
+        raise ValueError(f"gauge field of {U.size} elements, expected 4*V*9 for dims {tuple(dims)}")
+    return U
+
+
+def _spinors(psi, dims, single=False):
+    """psi as complex128 after checking that it holds whole spinor fields
+    (exactly one with single=True)."""
+    psi = _cplx(psi)
+    n = int(np.prod(dims)) * 12
+    if psi.size == 0 or psi.size % n or (single and psi.size != n):
+        raise ValueError(f"spinor array of {psi.size} elements, expected {'' if single else 'a multiple of '}"
+                         f"V*12 = {n} for dims {tuple(dims)}")
+    return psi
+
+
 def _ints(seq):
     seq = [int(v) for v in seq]
     return (ctypes.c_int * max(1, len(seq)))(*seq), len(seq)
@@ -93,8 +113,8 @@ def gamma(mask: int, basis: int = 0) -> np.ndarray:
 
 def hop(U, psi, dims, bc_t, out_parity=-1, dagger=False, basis=0):
     """Hopping term sum_mu [(1-g_mu)U_mu(x)psi(x+mu) + (1+g_mu)U_mu(x-mu)^+psi(x-mu)]."""
-    U = _cplx(U)
-    psi = _cplx(psi)
+    U = _gauge(U, dims)
+    psi = _spinors(psi, dims, single=True)
     out = np.zeros_like(psi)
     _load().or_hop(_dims(dims), bc_t, basis, _ptr(U), _ptr(psi), _ptr(out), out_parity,
                    int(dagger))
@@ -103,8 +123,8 @@ def hop(U, psi, dims, bc_t, out_parity=-1, dagger=False, basis=0):
 
 def apply_D(U, psi, dims, bc_t, kappa, dagger=False, basis=0):
     """Wilson-Dirac operator D = 1 - kappa*Hop (or D^+) applied to psi."""
-    U = _cplx(U)
-    psi = _cplx(psi)
+    U = _gauge(U, dims)
+    psi = _spinors(psi, dims)
     V = int(np.prod(dims))
     nrhs = psi.size // (V * 12)
     out = np.zeros_like(psi)
@@ -115,8 +135,8 @@ def apply_D(U, psi, dims, bc_t, kappa, dagger=False, basis=0):
 
 def apply_Dhat(U, psi_even, dims, bc_t, kappa, dagger=False, basis=0):
     """Schur operator 1 - kappa^2 H_eo H_oe on a full-lattice vector (odd part ignored)."""
-    U = _cplx(U)
-    psi = _cplx(psi_even)
+    U = _gauge(U, dims)
+    psi = _spinors(psi_even, dims, single=True)
     out = np.zeros_like(psi)
     _load().or_apply_Dhat(_dims(dims), bc_t, basis, kappa, _ptr(U), _ptr(psi), _ptr(out),
                           int(dagger))
@@ -129,8 +149,8 @@ def solve(U, b, dims, bc_t, kappa, tol=1e-13, max_iter=20000, method=0, basis=0)
     method 0: even-odd BiCGStab with CGNR fallback; 1: full BiCGStab;
     2: even-odd CGNR.  Returns (x, iters, resid, n_failed).
     """
-    U = _cplx(U)
-    b = _cplx(b)
+    U = _gauge(U, dims)
+    b = _spinors(b, dims)
     V = int(np.prod(dims))
     nrhs = b.size // (V * 12)
     x = np.zeros_like(b)
@@ -148,7 +168,7 @@ def loops_exact(U, dims, bc_t, kappa, t0, gammas, tol=1e-13, max_iter=20000, bas
 
     Returns L [ngamma][nt][Vs] (and S [nt][Vs][4][4] when want_S).
     """
-    U = _cplx(U)
+    U = _gauge(U, dims)
     t_arr, nt = _ints(t0)
     g_arr, ng = _ints(gammas)
     Vs = int(dims[0] * dims[1] * dims[2])
@@ -165,7 +185,7 @@ def loops_exact(U, dims, bc_t, kappa, t0, gammas, tol=1e-13, max_iter=20000, bas
 def loops_exact_sites(U, dims, bc_t, kappa, sites, gammas, tol=1e-13, max_iter=20000,
                       basis=0, want_S=False):
     """Exact loops at an explicit list of lexicographic sites: L [ngamma][nsites]."""
-    U = _cplx(U)
+    U = _gauge(U, dims)
     sites = np.ascontiguousarray(sites, dtype=np.int64)
     g_arr, ng = _ints(gammas)
     L = np.zeros((ng, sites.size), dtype=np.complex128)
@@ -199,7 +219,7 @@ def noise(noise_type, seed, r, dims):
 def loops_tsm(U, dims, bc_t, kappa, noise_type, seed, r0, n_lp, n_hp, tol_lp, tol_hp,
               dilution, t_begin, t_end, gammas, max_iter=20000, basis=0):
     """Truncated-solver-method estimate L [ngamma][t_end-t_begin][Vs]."""
-    U = _cplx(U)
+    U = _gauge(U, dims)
     g_arr, ng = _ints(gammas)
     Vs = int(dims[0] * dims[1] * dims[2])
     L = np.zeros((ng, t_end - t_begin, Vs), dtype=np.complex128)
@@ -224,7 +244,7 @@ def loops_grad(U, dims, bc_t, kappa, t0, gammas, w, tol=1e-13, max_iter=20000, b
     w: complex [ngamma][nt][Vs].  Returns (dU [4][V][3][3], dkappa) with
     dU = dF/dRe U + i dF/dIm U.
     """
-    U = _cplx(U)
+    U = _gauge(U, dims)
     t_arr, nt = _ints(t0)
     g_arr, ng = _ints(gammas)
     w = _cplx(w)

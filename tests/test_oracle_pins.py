@@ -615,3 +615,23 @@ def test_tsm_decomposes_into_lp_and_hp_ensembles():
     hp_lp = O.loops_tsm(*base, n_lp, n_hp, 0, tlp, tlp, 1 | 2, 0, 4, GAMMAS)
     assert np.abs(tsm - (lp + hp_hp - hp_lp)).max() < 1e-13
     assert np.abs(hp_hp - hp_lp).max() > 1e-6  # the correction is not vacuous
+
+
+def test_wrappers_reject_mis_sized_arrays():
+    """The C oracle trusts the sizes it is given: the Python wrappers refuse a
+    gauge field or spinor array that does not hold whole fields of the lattice
+    (a half-lattice vector handed to the Schur operator, which takes a
+    full-lattice vector, would otherwise be read and written past its end)."""
+    dims = (2, 2, 2, 4)
+    V = 32
+    U = S.random_links(dims, 0.3, 5)
+    psi = S.random_spinors(dims, 1, 6)[0]
+    O.apply_Dhat(U, psi, dims, -1, 0.1)  # well-formed call
+    with pytest.raises(ValueError):
+        O.apply_Dhat(U, psi[:V // 2], dims, -1, 0.1)
+    with pytest.raises(ValueError):
+        O.apply_D(U[:, :V // 2], psi, dims, -1, 0.1)
+    with pytest.raises(ValueError):
+        O.hop(U, S.random_spinors(dims, 2, 7), dims, -1)
+    with pytest.raises(ValueError):
+        O.solve(U, psi.reshape(-1)[:-12], dims, -1, 0.1)
