@@ -92,11 +92,12 @@ enum { FL_DIL_TIME = 1, FL_DIL_SPIN = 2, FL_DIL_COLOUR = 4, FL_DIL_EVENODD = 8,
  *              Sec. II; this is the narrowest storage offered here).
  *              For F32/BF16/H16 the iteration residual is replaced by the
  *              FP64 residual whenever it has dropped by `delta` since the
- *              last replacement (reliable updates): F32 and BF16 recompute
- *              b - Dx from the FP64 solution; H16 carries the FP64
- *              residual, subtracting D applied in FP64 to the 16-bit
- *              correction that it then adds to the FP64 solution.  Every
- *              solve's result is checked on the full operator in FP64.
+ *              last replacement (reliable updates): F32 and H16 carry the
+ *              FP64 residual, subtracting D applied in FP64 to the
+ *              low-precision correction that they then add to the FP64
+ *              solution; BF16 (and any restart after a breakdown)
+ *              recomputes b - Dx from the FP64 solution.  Every solve's
+ *              result is checked on the full operator in FP64.
  *  gauge_reals 18 (full links) or 12 (rows 0 and 1; row 2 rebuilt as
  *              conj(row0 x row1)) for the F32 inner operator; BF16 and H16
  *              need 12.
