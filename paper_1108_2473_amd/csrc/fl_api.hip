@@ -519,10 +519,15 @@ fl_status fl_create(fl_ctx **out, int device, const int dims[4], int bc_t)
     for (int mu = 0; mu < 4; ++mu)
         if (dims[mu] < 2 || dims[mu] % 2) return set_err(nullptr, FL_ERR_ARG, "lattice extents must be even and >= 2");
     if (bc_t != 1 && bc_t != -1) return set_err(nullptr, FL_ERR_ARG, "bc_t must be +1 or -1");
-    long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
     // kernels address a whole link array (8 x 144 bytes per site pair in
-    // FP64) through 32-bit buffer offsets
-    if ((V / 2) * 8 * 144 >= (1LL << 31)) return set_err(nullptr, FL_ERR_ARG, "lattice too large (V <= 3.7M sites)");
+    // FP64) through 32-bit buffer offsets; the volume is formed factor by
+    // factor so that no product of four extents can overflow
+    long long V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        V *= dims[mu];
+        if ((V / 2) * 8 * 144 >= (1LL << 31))
+            return set_err(nullptr, FL_ERR_ARG, "lattice too large (V <= 3.7M sites)");
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         (void)hipGetLastError();

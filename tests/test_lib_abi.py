@@ -47,9 +47,13 @@ def test_version_and_defaults(lib):
 
 
 def test_argument_checks_before_any_device_call(lib):
-    """Odd or too small extents and a bad bc_t are rejected before HIP is touched."""
+    """Odd or too small extents, a bad bc_t and lattices beyond the 32-bit
+    addressing of a link array (including extents whose product overflows
+    64 bits) are rejected before HIP is touched."""
     h = ctypes.c_void_p()
-    for dims, bc in [((3, 4, 4, 4), -1), ((4, 4, 4, 0), -1), ((4, 4, 4, 4), 0), ((2, 2, 2, 1), 1)]:
+    big = 1 << 30
+    for dims, bc in [((3, 4, 4, 4), -1), ((4, 4, 4, 0), -1), ((4, 4, 4, 4), 0), ((2, 2, 2, 1), 1),
+                     ((64, 64, 64, 64), -1), ((big, big, big, big), -1)]:
         d = (ctypes.c_int * 4)(*dims)
         assert lib.fl_create(ctypes.byref(h), 0, d, bc) == -1
         assert lib.fl_last_error(None)
