@@ -322,7 +322,7 @@ void prof_end(fl_ctx *c, int kernel, double bytes);
 // workspace slots
 enum {
     WS_CANON = 0, WS_BE, WS_BO, WS_XE, WS_XO, WS_BH, WS_RH, WS_T64, WS_R, WS_R0, WS_P, WS_V, WS_S,
-    WS_T, WS_XL, WS_TMP, WS_PART, WS_STATE, WS_ACTIVE, WS_MASK, WS_SITES, WS_GAM, WS_ACC,
+    WS_T, WS_XL, WS_TMP, WS_PART, WS_STATE, WS_MASK, WS_SITES, WS_GAM, WS_ACC,
     WS_ACC2, WS_COMP, WS_M, WS_CE, WS_CO, WS_DU, WS_HE, WS_HO, WS_XE2, WS_XO2, WS_MISC,
     WS_CORR_A, WS_CORR_B, WS_CORR_OUT, WS_CORR_IDX, WS_SM_E0, WS_SM_O0, WS_SM_E1, WS_SM_O1, WS_PI_SRC,
     WS_PI_SOL, WS_PI_RHO, WS_APE0, WS_APE1,

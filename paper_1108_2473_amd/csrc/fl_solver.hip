@@ -315,8 +315,10 @@ fl_status Solver::prepare()
         pos_k2[l] = c->kappa * c->kappa;
     }
     partial = (double *)ws_get(c0, WS_PART, sizeof(double) * 6 * (size_t)nsys * B.nsb_max);
-    dst = (SysState *)ws_get(c0, WS_STATE, sizeof(SysState) * nsys);
-    active = (int *)ws_get(c0, WS_ACTIVE, sizeof(int) * nsys);
+    // [SysState x nsys][active x nsys] in one block, laid out like the
+    // page-locked host copy below, so one transfer fetches both at a check
+    dst = (SysState *)ws_get(c0, WS_STATE, (sizeof(SysState) + sizeof(int)) * nsys);
+    active = dst ? (int *)(dst + nsys) : nullptr;
     mask = (int *)ws_get(c0, WS_MASK, sizeof(int) * nsys);
     if (!partial || !dst || !active || !mask) return set_err(c0, FL_ERR_NOMEM, "device allocation failed");
     {
@@ -495,11 +497,10 @@ fl_status Solver::run(std::vector<SysResult> &res)
                 else
                     bicg_iteration();
             }
-        if ((e = hip_check(c0, hipMemcpyAsync(hst.data(), dst, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, st),
+        // state and active flags in one transfer (adjacent on both sides)
+        if ((e = hip_check(c0, hipMemcpyAsync(hst.data(), dst, (sizeof(SysState) + sizeof(int)) * nsys,
+                                              hipMemcpyDeviceToHost, st),
                            "download state")))
-            return e;
-        if ((e = hip_check(c0, hipMemcpyAsync(hact.data(), active, sizeof(int) * nsys, hipMemcpyDeviceToHost, st),
-                           "download active")))
             return e;
         if ((e = hip_check(c0, hipStreamSynchronize(st), "sync"))) return e;
         if ((e = hip_check(c0, hipGetLastError(), "solver launch"))) return e;
