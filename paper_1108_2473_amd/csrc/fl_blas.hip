@@ -408,6 +408,23 @@ __device__ __forceinline__ void scal_step(const ScalArgs &a, const double P[6], 
     }
 }
 
+// the partial-sum slots each scalar step reads (bit k: slot k)
+__device__ __forceinline__ int scal_slots(int step)
+{
+    switch (step) {
+    case SC_ALPHA: return 0x03;     // <r0, v>
+    case SC_OMEGA: return 0x07;     // <t, s>, |t|^2
+    case SC_BETA: return 0x07;      // <r0, r>, |r|^2
+    case SC_RESET: return 0x3c;     // |rh|^2, <r0, r>, |r|^2
+    case SC_INIT: return 0x38;      // <r0, r>, |r|^2
+    case SC_CG_INIT: return 0x24;   // |z|^2, |r|^2
+    case SC_CG_ALPHA: return 0x04;  // |q|^2
+    case SC_CG_BETA: return 0x24;   // |z|^2, |r|^2 (if carried)
+    case SC_CG_REZ: return 0x27;    // <z, p>, |z|^2, |r|^2
+    default: return 0x3f;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_scal(ScalArgs a)
 {
     const int sys = blockIdx.x;
@@ -422,7 +439,10 @@ __global__ __launch_bounds__(256) void k_scal(ScalArgs a)
     const int nsb = a.B.lat[l].nsb, nb = a.B.nsb_max;
     __shared__ double red[6][256];
     __shared__ SysState snew;
+    // only the slots this step reads (the same for the whole block)
+    const int used = scal_slots(a.step);
     for (int slot = 0; slot < 6; ++slot) {
+        if (!((used >> slot) & 1)) continue;
         double acc = 0;
         for (int sb = threadIdx.x; sb < nsb; sb += 256) acc += a.partial[pidx(slot, a.nsys, sys, nb, sb)];
         red[slot][threadIdx.x] = acc;
@@ -430,13 +450,14 @@ __global__ __launch_bounds__(256) void k_scal(ScalArgs a)
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
-            for (int slot = 0; slot < 6; ++slot) red[slot][threadIdx.x] += red[slot][threadIdx.x + w];
+            for (int slot = 0; slot < 6; ++slot)
+                if ((used >> slot) & 1) red[slot][threadIdx.x] += red[slot][threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x >= FL_WAVE) return;
     if (threadIdx.x == 0) {
         double P[6];
-        for (int slot = 0; slot < 6; ++slot) P[slot] = red[slot][0];
+        for (int slot = 0; slot < 6; ++slot) P[slot] = ((used >> slot) & 1) ? red[slot][0] : 0.0;
         SysState s = a.st[sys];
         const int act0 = a.active[sys];
         int act = act0;
