@@ -303,6 +303,8 @@ def main():
         neg = [(-a, -b, -c) for a, b, c in mom]
         L1 = torch.from_numpy(loops[0]).cuda()
         L2 = torch.from_numpy(loops[1]).cuda()
+        lat.disconnected_corr(lat.momentum_project(L1, mom), lat.momentum_project(L2, neg),
+                              [(g, g) for g in range(len(gam))])  # warm-up (allocations)
         torch.cuda.synchronize()
         tc = time.perf_counter()
         P1 = lat.momentum_project(L1, mom)

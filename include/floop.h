@@ -342,7 +342,8 @@ fl_status fl_autotune(fl_ctx *ctx, int prec, int gauge_reals, int nrhs, int *rt,
  * output of fl_loops_exact or fl_loops_stochastic; site x = (x, y, z) with x
  * fastest), Lp: [ngamma][nmom][nt][2]; 1 <= ngamma <= 16.  L and Lp are
  * both on the host or both on the device (`where`); mom is a host array.
- * Needs no gauge field.  FP64, summed in a fixed order (deterministic). */
+ * Needs no gauge field and Lx + Ly + Lz <= 1024 (FL_ERR_ARG otherwise).
+ * FP64, summed in a fixed order (deterministic). */
 fl_status fl_momentum_project(fl_ctx *ctx, const double *L, int ngamma, int nt, const int *mom,
                               int nmom, double *Lp, fl_where where);
 
@@ -390,7 +391,8 @@ fl_status fl_ape_smear(fl_ctx *ctx, double alpha, int n, double *Uout, fl_where 
  *   phi = F_sink D^-1 F_source e_{y0, b, beta}  (g5-hermiticity),
  * t counted from the source timeslice t0 (mod T); mom: nmom integer vectors
  * (host); C: [nmom][T][2] on the host or the device (`where`).  The 12
- * solves use params p (stopping rule on the full operator).  With local
+ * solves use params p (stopping rule on the full operator).  Needs
+ * Lx + Ly + Lz <= 1024, as fl_momentum_project.  With local
  * fields (no smearing) and the disconnected part D(t) of
  * fl_disconnected_corr at p = 0 and Gamma = g5, the flavour-singlet
  * correlator of two degenerate flavours is C_pi(t) - 2 D(t). */

@@ -4,11 +4,13 @@
 //   Lp_G(p, t) = sum_x exp(+i p.x) L_G(x, t),  p = 2 pi (n_x/Lx, n_y/Ly, n_z/Lz)
 //   D_AB(p, t) = (1/V_s)(1/T) sum_ti Lp_A(p, ti + t) Lp_B(-p, ti)
 //
-// The phase of site x for the integer vector n is exp(2 pi i r / V_s) with
-// r = (n_x x V_s/Lx + n_y y V_s/Ly + n_z z V_s/Lz) mod V_s, evaluated by
-// sincospi on the exactly reduced argument 2r/V_s.  Sums run in FP64 in a
-// fixed order (per-thread partial sums over a strided site range, then a
-// fixed tree in LDS), so results do not depend on the launch.
+// The phase of site x for the integer vector n is the product of the three
+// per-axis factors exp(2 pi i r_mu / L_mu), r_mu = (n_mu x_mu) mod L_mu,
+// each evaluated once per workgroup by sincospi on the exactly reduced
+// argument 2 r_mu / L_mu and kept in LDS (two complex products per site
+// instead of a sine and cosine).  Sums run in FP64 in a fixed order
+// (per-thread partial sums over a strided site range, then a fixed tree in
+// LDS), so results do not depend on the launch.
 #include <cstring>
 #include <vector>
 
@@ -16,8 +18,10 @@
 
 namespace {
 
-constexpr int MAXG = 16;  // Gamma matrices per call
+constexpr int MAXG = 16;    // Gamma matrices per call
 constexpr int BLK = 256;
+constexpr int MAXAX = 1024;  // Lx + Ly + Lz: the per-axis phase tables in LDS (16 KB)
+constexpr int GB = 4;        // Gamma matrices per workgroup of the projection
 
 struct MomArgs {
     const double2 *L;  // [ngamma][nt][Vs]
@@ -26,33 +30,57 @@ struct MomArgs {
     int ngamma, nt, nmom, Lx, Ly, Lz, Vs;
 };
 
-// one workgroup per (timeslice, momentum)
+// one workgroup per (timeslice, momentum, group of up to GB Gammas), in
+// XCD-contiguous order with the Gamma group innermost, then the momentum:
+// each XCD takes a run of timeslices, so a timeslice's loops (ngamma x V_s
+// values) come from HBM once and then from that XCD's L2 for every
+// momentum.  The group's GB loads per site are unconditional (an index past
+// the last Gamma repeats it; its sum is not stored), so they are all in
+// flight together.
 __global__ __launch_bounds__(BLK) void k_momproj(MomArgs a)
 {
-    const int t = blockIdx.x % a.nt, k = blockIdx.x / a.nt;
-    const long long nx = a.mom[3 * k], ny = a.mom[3 * k + 1], nz = a.mom[3 * k + 2];
-    const long long Vs = a.Vs, sx = Vs / a.Lx, sy = Vs / a.Ly, sz = Vs / a.Lz;
-    double2 acc[MAXG];
-#pragma unroll
-    for (int g = 0; g < MAXG; ++g) acc[g] = make_double2(0.0, 0.0);
-    for (int xs = threadIdx.x; xs < a.Vs; xs += BLK) {
-        const int x = xs % a.Lx, y = (xs / a.Lx) % a.Ly, z = xs / (a.Lx * a.Ly);
-        long long r = (nx * x * sx + ny * y * sy + nz * z * sz) % Vs;
-        if (r < 0) r += Vs;
+    const int ngr = (a.ngamma + GB - 1) / GB;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, 0);
+    const int g0 = (tile % ngr) * GB, k = (tile / ngr) % a.nmom, t = tile / (ngr * a.nmom);
+    // exp(2 pi i n_mu x_mu / L_mu) for x_mu = 0..L_mu-1, the three axes in a row
+    __shared__ double2 ph[MAXAX];
+    const int nL = a.Lx + a.Ly + a.Lz;
+    for (int i = threadIdx.x; i < nL; i += BLK) {
+        const int mu = i < a.Lx ? 0 : (i < a.Lx + a.Ly ? 1 : 2);
+        const int L = mu == 0 ? a.Lx : (mu == 1 ? a.Ly : a.Lz);
+        const int x = i - (mu == 0 ? 0 : (mu == 1 ? a.Lx : a.Lx + a.Ly));
+        long long r = ((long long)a.mom[3 * k + mu] * x) % L;
+        if (r < 0) r += L;
         double sn, cs;
-        sincospi(2.0 * (double)r / (double)Vs, &sn, &cs);
+        sincospi(2.0 * (double)r / (double)L, &sn, &cs);
+        ph[i] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    const double2 *src[GB];
 #pragma unroll
-        for (int g = 0; g < MAXG; ++g)
-            if (g < a.ngamma) {
-                const double2 v = a.L[((size_t)g * a.nt + t) * a.Vs + xs];
-                acc[g].x += cs * v.x - sn * v.y;
-                acc[g].y += cs * v.y + sn * v.x;
-            }
+    for (int j = 0; j < GB; ++j) src[j] = a.L + ((size_t)min(g0 + j, a.ngamma - 1) * a.nt + t) * a.Vs;
+    double2 acc[GB];
+#pragma unroll
+    for (int j = 0; j < GB; ++j) acc[j] = make_double2(0.0, 0.0);
+    for (int xs = threadIdx.x; xs < a.Vs; xs += BLK) {
+        double2 v[GB];
+#pragma unroll
+        for (int j = 0; j < GB; ++j) v[j] = src[j][xs];
+        const int xy = xs / a.Lx, x = xs - xy * a.Lx, z = xy / a.Ly, y = xy - z * a.Ly;
+        const double2 px = ph[x], py = ph[a.Lx + y], pz = ph[a.Lx + a.Ly + z];
+        const double ar = px.x * py.x - px.y * py.y, ai = px.x * py.y + px.y * py.x;
+        const double cs = ar * pz.x - ai * pz.y, sn = ar * pz.y + ai * pz.x;
+#pragma unroll
+        for (int j = 0; j < GB; ++j) {
+            acc[j].x += cs * v[j].x - sn * v[j].y;
+            acc[j].y += cs * v[j].y + sn * v[j].x;
+        }
     }
     __shared__ double2 red[BLK];
-    __shared__ double2 res[MAXG];
-    for (int g = 0; g < a.ngamma; ++g) {
-        red[threadIdx.x] = acc[g];
+    __shared__ double2 res[GB];
+#pragma unroll
+    for (int j = 0; j < GB; ++j) {
+        red[threadIdx.x] = acc[j];
         __syncthreads();
         for (int w = BLK / 2; w > 0; w >>= 1) {
             if ((int)threadIdx.x < w) {
@@ -61,11 +89,12 @@ __global__ __launch_bounds__(BLK) void k_momproj(MomArgs a)
             }
             __syncthreads();
         }
-        if (threadIdx.x == 0) res[g] = red[0];
+        if (threadIdx.x == 0) res[j] = red[0];
         __syncthreads();
     }
-    // one store instruction (lane g writes Gamma g), which ends the kernel
-    if ((int)threadIdx.x < a.ngamma) a.Lp[((size_t)threadIdx.x * a.nmom + k) * a.nt + t] = res[threadIdx.x];
+    // one store instruction (lane j writes Gamma g0 + j), which ends the kernel
+    if ((int)threadIdx.x < GB && g0 + (int)threadIdx.x < a.ngamma)
+        a.Lp[((size_t)(g0 + threadIdx.x) * a.nmom + k) * a.nt + t] = res[threadIdx.x];
 }
 
 struct CorrArgs {
@@ -97,11 +126,14 @@ unsigned blocks(long long n) { return (unsigned)((n + BLK - 1) / BLK); }
 
 }  // namespace
 
+bool momproj_fits(const int L4[4]) { return L4[0] + L4[1] + L4[2] <= MAXAX; }
+
 void launch_momproj(const double2 *L, double2 *Lp, const int *dmom, int ngamma, int nt, int nmom, const int L4[4],
                     hipStream_t s)
 {
     MomArgs a{L, Lp, dmom, ngamma, nt, nmom, L4[0], L4[1], L4[2], L4[0] * L4[1] * L4[2]};
-    hipLaunchKernelGGL(k_momproj, dim3((unsigned)(nt * nmom)), dim3(BLK), 0, s, a);
+    const int ngr = (ngamma + GB - 1) / GB;
+    hipLaunchKernelGGL(k_momproj, dim3((unsigned)(nt * nmom * ngr)), dim3(BLK), 0, s, a);
 }
 
 fl_status fl_momentum_project(fl_ctx *c, const double *L, int ngamma, int nt, const int *mom, int nmom, double *Lp,
@@ -110,6 +142,7 @@ fl_status fl_momentum_project(fl_ctx *c, const double *L, int ngamma, int nt, co
     if (!c) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
     if (ngamma < 1 || ngamma > MAXG || nt < 1 || nmom < 1 || !L || !Lp || !mom)
         return set_err(c, FL_ERR_ARG, "need 1..16 Gammas, nt >= 1, nmom >= 1 and non-NULL arrays");
+    if (!momproj_fits(c->L)) return set_err(c, FL_ERR_ARG, "momentum projection needs Lx + Ly + Lz <= 1024");
     if (where != FL_HOST && where != FL_DEVICE) return set_err(c, FL_ERR_ARG, "bad `where`");
     hipSetDevice(c->device);
     const int Vs = c->L[0] * c->L[1] * c->L[2];

@@ -172,6 +172,8 @@ void launch_su3_check(const double *canon, double *dev_max, long long nlinks, hi
 // arrays; dmom: device [nmom][3]) on stream s
 void launch_momproj(const double2 *L, double2 *Lp, const int *dmom, int ngamma, int nt, int nmom, const int L4[4],
                     hipStream_t s);
+// the spatial extents the projection's per-axis phase tables hold (Lx + Ly + Lz <= 1024)
+bool momproj_fits(const int L4[4]);
 void launch_point_sources(double2 *even, double2 *odd, const long long *sites, int nsites,
                           const LatGeom &g, hipStream_t s);
 

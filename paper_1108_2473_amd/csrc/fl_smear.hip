@@ -348,6 +348,7 @@ fl_status fl_pion_corr(fl_ctx *c, long long y0, const fl_solver_params *p, doubl
     if (!c) return set_err(nullptr, FL_ERR_ARG, "ctx is NULL");
     if (y0 < 0 || y0 >= c->V) return set_err(c, FL_ERR_ARG, "source site outside the lattice");
     if (nmom < 1 || !mom || !C || !p) return set_err(c, FL_ERR_ARG, "need params, nmom >= 1, mom and C");
+    if (!momproj_fits(c->L)) return set_err(c, FL_ERR_ARG, "momentum projection needs Lx + Ly + Lz <= 1024");
     if ((smear_source || smear_sink) && (n < 0 || !(norm > 0) || !std::isfinite(alpha)))
         return set_err(c, FL_ERR_ARG, "bad smearing arguments (n >= 0, norm > 0, finite alpha)");
     if (where != FL_HOST && where != FL_DEVICE) return set_err(c, FL_ERR_ARG, "bad `where`");

@@ -43,6 +43,21 @@ def test_projection_and_correlator_random(F, dims):
     lat.close()
 
 
+@pytest.mark.parametrize("ng", [1, 3, 4, 5, 16])
+def test_projection_gamma_counts(F, ng):
+    """The projection handles the Gamma matrices in groups of four per
+    workgroup: one, a partial group, exactly one group, a group and one more,
+    and the maximum of sixteen, on a lattice with unequal spatial extents."""
+    dims = (6, 4, 8, 4)
+    Vs, T = 6 * 4 * 8, 4
+    lat = F.Lattice(dims, -1)
+    L = _rand((ng, T, Vs), 20 + ng)
+    P = lat.momentum_project(L, MOM)
+    assert P.shape == (ng, len(MOM), T)
+    assert np.abs(P - O.momentum_project(L, dims, MOM)).max() <= 1e-12 * np.sqrt(Vs)
+    lat.close()
+
+
 def test_device_arrays_and_argument_checks(F):
     import torch
     dims = (4, 4, 4, 8)
