@@ -23,6 +23,7 @@
 namespace {
 
 constexpr int BLK = 256;
+constexpr int SM_RT = BLK / FL_WAVE;  // right-hand sides per smearing workgroup
 constexpr double kPi = 3.14159265358979323846;
 
 struct SmearArgs {
@@ -51,13 +52,21 @@ __device__ __forceinline__ void colour_hop(cx<double> acc[12], const cx<double> 
         }
 }
 
-// one step of (1 + alpha H) / norm for the sites of parity `par`
+// one step of (1 + alpha H) / norm for the sites of parity `par`.  A
+// workgroup is a tile of FL_WAVE sites x SM_RT right-hand sides (one wave
+// each), tiles in XCD-contiguous order with the right-hand-side groups of a
+// site block consecutive: the links of a site block are read by its waves
+// within one CU and one XCD's L2 instead of once per right-hand side from
+// HBM (in site-major order a site's right-hand sides were Vh / BLK
+// workgroups apart, on different XCDs)
 __global__ __launch_bounds__(BLK) void k_smear(SmearArgs a)
 {
     const LatGeom &g = a.g;
-    const long long id = blockIdx.x * (long long)BLK + threadIdx.x;
-    if (id >= (long long)a.nrhs * g.Vh) return;
-    const int rhs = (int)(id / g.Vh), i = (int)(id - (long long)rhs * g.Vh);
+    const int nrg = (a.nrhs + SM_RT - 1) / SM_RT;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, 0);
+    const int sb = tile / nrg, rg = tile - sb * nrg;
+    const int rhs = rg * SM_RT + (int)threadIdx.x / FL_WAVE, i = sb * FL_WAVE + (int)threadIdx.x % FL_WAVE;
+    if (rhs >= a.nrhs || i >= g.Vh) return;
     const size_t fs = (size_t)12 * g.Vh;
     const Coord c = cb_coords(g, a.par, i);
     cx<double> acc[12], psi[12], U[3][3];
@@ -299,7 +308,8 @@ fl_status smear_canon(fl_ctx *c, double *canon, int nrhs, double alpha, int n, d
     if (!e0 || !o0 || !e1 || !o1 || !gauge) return set_err(c, FL_ERR_NOMEM, "device allocation failed (smearing)");
     LatGeom g = lat_geom(c, nrhs);
     launch_canon_to_eo(canon, e0, o0, g, nrhs, c->stream);
-    const unsigned nb = blocks((long long)nrhs * c->Vh);
+    // tiles of FL_WAVE sites x SM_RT right-hand sides
+    const unsigned nb = (unsigned)(((c->Vh + FL_WAVE - 1) / FL_WAVE) * (long long)((nrhs + SM_RT - 1) / SM_RT));
     for (int k = 0; k < n; ++k) {
         SmearArgs a{e0, o0, e1, gauge, g, nrhs, 0, alpha, 1.0 / norm};
         hipLaunchKernelGGL(k_smear, dim3(nb), dim3(BLK), 0, c->stream, a);
