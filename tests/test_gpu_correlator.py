@@ -69,6 +69,11 @@ def test_device_arrays_and_argument_checks(F):
     with pytest.raises(F.FloopError):
         lat.disconnected_corr(Pd, Pd, [(0, 2)])  # Gamma index out of range
     lat.close()
+    # spatial extents beyond the projection's phase tables (Lx + Ly + Lz <= 1024)
+    wide = F.Lattice((1022, 2, 2, 2), -1)
+    with pytest.raises(F.FloopError):
+        wide.momentum_project(_rand((1, 2, 1022 * 4), 14), MOM)
+    wide.close()
 
 
 def test_exact_loop_correlator_4x4x4x8(F):
